@@ -1,0 +1,374 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these tests re-types the oracle's own formula: each compares it with
+something computed a different way (brute force, a closed form, a textbook
+identity, a dense-matrix propagator, a printed number of the paper).
+
+  P1  basis == brute-force filter of {0..N}^M sorted lexicographically
+  P2  sector sizes == closed form from Ramanujan sums (multisets of Z_M)
+  P3  Hermiticity of H for symmetric V; scatter form == gather form
+  P4  Lambda = 0: H is diagonal with E(n) = sum w n; RK4 multiplies by R(-iE dt)^s
+  P5  contact interaction, w = 0: spectrum (Lambda M/2) sum_x n_x(n_x - 1) and
+      site-wise Kerr dynamics of a coherent state
+  P6  single-mode Kerr closed forms for <a>, <a^2>, Q
+  P7  dense RK4 propagator and dense expm
+  P8  momentum conservation (block structure), norm/energy within the RK4 bound
+  P9  coherent state at t = 0 (Q = 0, lambda_p = n_tot, V_- = 1, normal order)
+  P10 the paper's long-range coherent test problem, n_tot |chi| (Sec. IV.E)
+  P11 field-number and number eigenstates (Sec. II.B, Sec. IV.C/D remarks)
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle, count_sector
+from oracle import dense, derived, evolve, states
+
+
+# --------------------------------------------------------------------- P1 --
+@pytest.mark.parametrize("M,N,pmod", [(1, 5, 1), (2, 6, 2), (3, 5, 3), (4, 6, 4), (5, 4, 5), (4, 5, 7), (3, 6, 13)])
+def test_p1_basis_bruteforce(oracle_lib, M, N, pmod):
+    brute = [n for n in itertools.product(range(N + 1), repeat=M) if sum(n) == N]
+    for P in range(pmod):
+        want = sorted(n for n in brute if sum(j * x for j, x in enumerate(n)) % pmod == P)
+        o = Oracle(M, pmod, np.zeros(M), 0.0, np.zeros((M,) * 4), [(N, P)])
+        got = [tuple(int(v) for v in r) for r in o.occupations(0)]
+        assert got == want
+        if want:
+            idx = o.rank(0, np.array(want, dtype=np.uint8))
+            assert list(idx) == list(range(len(want)))
+
+
+# --------------------------------------------------------------------- P2 --
+def _ramanujan(d, P):
+    return sum(math.cos(2 * math.pi * a * P / d) for a in range(1, d + 1) if math.gcd(a, d) == 1)
+
+
+def closed_form_dim(M, N, P):
+    """Multisets of size N from Z_M with element sum == P (mod M):
+    (1/M) sum_{d | gcd(M, N)} c_d(P) C(N/d + M/d - 1, M/d - 1), c_d = Ramanujan sum."""
+    tot = 0.0
+    for d in range(1, M + 1):
+        if M % d == 0 and N % d == 0:
+            tot += _ramanujan(d, P) * math.comb(N // d + M // d - 1, M // d - 1)
+    return int(round(tot / M))
+
+
+@pytest.mark.parametrize("M,N", [(5, 8), (6, 12), (8, 12), (4, 9), (10, 6), (6, 30)])
+def test_p2_sector_sizes_closed_form(oracle_lib, M, N):
+    dims = [count_sector(M, M, N, P) for P in range(M)]
+    assert dims == [closed_form_dim(M, N, P) for P in range(M)]
+    assert sum(dims) == math.comb(N + M - 1, M - 1)
+
+
+def test_p2_workload_sizes(oracle_lib):
+    # tiny number state sector (M=5, N=8, P=2) and its whole N=8 space
+    assert count_sector(5, 5, 8, 2) == 99
+    assert sum(count_sector(5, 5, 8, P) for P in range(5)) == 495
+    # one large sector: M=8, N=48, P=0, by enumeration and by closed form
+    assert closed_form_dim(8, 48, 0) == 25_366_335
+    assert count_sector(8, 8, 48, 0) == 25_366_335
+    # batched coherent: M=6, N <= 90, all P
+    assert sum(closed_form_dim(6, N, P) for N in range(91) for P in range(6)) == math.comb(96, 6)
+    # field-number draws: M=10, N=30, all P
+    assert sum(closed_form_dim(10, 30, P) for P in range(10)) == math.comb(39, 9)
+
+
+# --------------------------------------------------------------------- P3 --
+def _small_model(M=4, N=(3, 4, 5), seed=7, sym=True):
+    V = W.V_random_symmetric(M, seed) if sym else W.V_random(M, seed)
+    omega = np.random.default_rng(seed + 1).uniform(-1, 1, M)
+    secs = [(n, p) for n in N for p in range(M)]
+    return Oracle(M, M, omega, 0.7, V, secs)
+
+
+def test_p3_hermitian(oracle_lib):
+    o = _small_model()
+    x = W.random_psi(o.total, 1)
+    y = W.random_psi(o.total, 2)
+    lhs = np.vdot(x, o.apply_h(y))
+    rhs = np.vdot(o.apply_h(x), y)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+def test_p3_scatter_equals_gather(oracle_lib):
+    for sym in (True, False):
+        o = _small_model(sym=sym)
+        x = W.random_psi(o.total, 3)
+        full = o.apply_h(x)
+        rows = np.arange(o.total)
+        np.testing.assert_allclose(o.apply_h_rows(x, rows), full, rtol=0, atol=1e-12 * np.abs(full).max())
+
+
+def test_p3_nonsymmetric_v_transpose(oracle_lib):
+    """H(V[k,l,i,j]) is the transpose of H(V): <x, H y> = <H' x, y> for real x-conjugation."""
+    o = _small_model(sym=False)
+    oT = o.transposed()
+    x = W.random_psi(o.total, 4)
+    y = W.random_psi(o.total, 5)
+    assert abs(np.vdot(x, o.apply_h(y)) - np.vdot(oT.apply_h(x), y)) < 1e-12 * np.linalg.norm(x) * np.linalg.norm(y) * 10
+
+
+# --------------------------------------------------------------------- P4 --
+def test_p4_free_evolution(oracle_lib):
+    M = 5
+    omega = W.omega_quadratic(M)
+    o = Oracle(M, M, omega, 0.0, W.V_contact(M), [(6, p) for p in range(M)])
+    psi0 = W.random_psi(o.total, 11)
+    E = o.all_occupations().astype(float) @ omega
+    np.testing.assert_allclose(o.apply_h(psi0), E * psi0, rtol=1e-15, atol=0)
+    dt, s = 0.01, 50
+    z = -1j * E * dt
+    R = 1 + z + z ** 2 / 2 + z ** 3 / 6 + z ** 4 / 24
+    psi, _ = evolve.rk4(o, psi0, dt, s)
+    np.testing.assert_allclose(psi, R ** s * psi0, rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------- P5 --
+def test_p5_contact_spectrum(oracle_lib):
+    M, N, Lam = 4, 5, 0.3
+    o = Oracle(M, M, np.zeros(M), Lam, W.V_contact(M), [(N, p) for p in range(M)])
+    H = dense.dense_h(o)
+    ev = np.sort(np.linalg.eigvalsh(H))
+    pos = [x for x in itertools.product(range(N + 1), repeat=M) if sum(x) == N]
+    want = np.sort([0.5 * Lam * M * sum(n * (n - 1) for n in x) for x in pos])
+    np.testing.assert_allclose(ev, want, rtol=0, atol=1e-12)
+
+
+def test_p5_contact_coherent_sitewise_kerr(oracle_lib):
+    M, Lam, Nmax = 3, 0.4, 14
+    alpha = W.coherent_amplitudes(21, M, 1.0)
+    o = Oracle(M, M, np.zeros(M), Lam, W.V_contact(M), W.all_sectors(M, Nmax))
+    psi0 = states.coherent_state(o, alpha)
+    H = dense.dense_h(o)
+    F = np.exp(2j * np.pi * np.outer(np.arange(M), np.arange(M)) / M) / math.sqrt(M)  # b = F a
+    beta = F @ alpha
+    for t in (0.3, 1.1):
+        psi = dense.expm_evolve(H, psi0, t)
+        obs = derived.observe(o, psi)
+        b_t = beta * np.exp(np.abs(beta) ** 2 * (np.exp(-1j * Lam * M * t) - 1))
+        a_t = F.conj().T @ b_t
+        np.testing.assert_allclose(obs["a"], a_t, rtol=0, atol=1e-9)
+
+
+# --------------------------------------------------------------------- P6 --
+def test_p6_single_mode_kerr(oracle_lib):
+    Lam, alpha, Nmax, dt, nsteps = 0.1, 1.3 + 0.9j, 40, 1e-3, 2000
+    o = Oracle(1, 1, np.zeros(1), Lam, np.ones((1, 1, 1, 1)), [(n, 0) for n in range(Nmax + 1)])
+    psi0 = states.coherent_state(o, [alpha])
+    a2 = abs(alpha) ** 2
+
+    def check(step, t, psi):
+        obs = derived.observe(o, psi)
+        a_want = alpha * np.exp(a2 * (np.exp(-1j * Lam * t) - 1))
+        aa_want = alpha ** 2 * np.exp(-1j * Lam * t) * np.exp(a2 * (np.exp(-2j * Lam * t) - 1))
+        Q_want = 1 - np.exp(-2 * a2 * (1 - np.cos(Lam * t)))
+        assert abs(obs["a"][0] - a_want) < 1e-10
+        assert abs(obs["A"][0, 0] - aa_want) < 1e-10
+        assert abs(obs["n_tot"] - a2) < 1e-10
+        assert abs(obs["Q"] - Q_want) < 1e-10
+        return obs
+
+    _, outs = evolve.rk4(o, psi0, dt, nsteps, every=500, observe=check)
+    assert len(outs) == 5
+
+
+# --------------------------------------------------------------------- P7 --
+def test_p7_dense_rk4_and_expm(oracle_lib):
+    w = W.tiny_number()
+    o = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    psi0 = states.number_state(o, w.init_params)
+    H = dense.dense_h(o)
+    nsteps = 200
+    psi, _ = evolve.rk4(o, psi0, w.dt, nsteps)
+    np.testing.assert_allclose(psi, dense.rk4_dense_evolve(H, psi0, w.dt, nsteps), rtol=0, atol=1e-12)
+    Emax = np.abs(np.linalg.eigvalsh(H)).max()
+    T = nsteps * w.dt
+    bound = 4 * T * (Emax * w.dt) ** 4 * Emax / 120 + 1e-13
+    assert np.linalg.norm(psi - dense.expm_evolve(H, psi0, T)) <= bound
+
+
+# --------------------------------------------------------------------- P8 --
+def test_p8_momentum_blocks_and_conservation(oracle_lib):
+    M, N = 5, 6
+    for V in (W.V_contact(M), W.V_longrange(M)):
+        o = Oracle(M, M, W.omega_quadratic(M), 0.2, V, [(N, p) for p in range(M)])
+        H = dense.dense_h(o)
+        for a in range(M):
+            for b in range(M):
+                if a != b:
+                    blk = H[o.offsets[a]:o.offsets[a] + o.dims[a], o.offsets[b]:o.offsets[b] + o.dims[b]]
+                    assert np.all(blk == 0)
+        assert np.allclose(H, H.conj().T, atol=1e-14)
+    # norm and energy drift under RK4 bounded by |R(ix)|^2 = 1 - x^6/72 + x^8/576
+    psi0 = W.random_psi(o.total, 9)
+    psi0 /= np.linalg.norm(psi0)
+    dt, nsteps = 2e-3, 300
+    psi, _ = evolve.rk4(o, psi0, dt, nsteps)
+    xmax = np.abs(np.linalg.eigvalsh(H)).max() * dt
+    assert 0 <= 1 - np.linalg.norm(psi) ** 2 <= nsteps * xmax ** 6 / 72 + 1e-13
+    E0 = np.vdot(psi0, o.apply_h(psi0)).real
+    E1 = np.vdot(psi, o.apply_h(psi)).real
+    assert abs(E1 - E0) <= nsteps * xmax ** 6 / 72 * np.abs(np.linalg.eigvalsh(H)).max() + 1e-12
+
+
+# --------------------------------------------------------------------- P9 --
+def test_p9_coherent_initial_moments(oracle_lib):
+    M, Lam = 4, 0.3
+    alpha = W.coherent_amplitudes(5, M, 2.0)
+    V = W.V_longrange(M)
+    o = Oracle(M, M, np.zeros(M), Lam, V, W.all_sectors(M, 22))
+    psi0 = states.coherent_state(o, alpha)
+    obs = derived.observe(o, psi0)
+    tail = 1 - obs["norm2"]
+    assert 0 <= tail < 1e-9
+    assert abs(obs["Q"]) < 1e-8
+    assert abs(obs["n_tot"] - np.sum(np.abs(alpha) ** 2)) < 1e-7
+    assert abs(obs["lambda_p"] - obs["n_tot"]) < 1e-8
+    assert abs(obs["vminus"] - 1) < 1e-7
+    np.testing.assert_allclose(obs["M"], np.outer(alpha.conj(), alpha), atol=1e-7)
+    # normal-ordered interaction energy
+    Eint = np.vdot(psi0, o.apply_h(psi0)).real / obs["norm2"]
+    want = 0.5 * Lam * np.einsum("ijkl,i,j,k,l->", V, alpha.conj(), alpha.conj(), alpha, alpha).real
+    assert abs(Eint - want) < 1e-7 * max(1, abs(want))
+
+
+# -------------------------------------------------------------------- P10 --
+def test_p10_long_range_interaction_energy(oracle_lib):
+    """Sec. IV.E: n_tot |chi| of the long-range coherent test problem equals
+    |0.13 + 0.08 sqrt(2) cos(theta1 + theta3 - 2 theta2)| (independent of r), whose
+    maximum 0.243 covers the printed value 0.242."""
+    M = 5
+    V = W.V_longrange(M)
+    rng = np.random.default_rng(12)
+    for r in (1.0, 3.0):
+        C = -0.1 / r
+        for _ in range(4):
+            th = rng.uniform(0, 2 * np.pi, 3)
+            z = np.array([0, math.sqrt(2 * r) * np.exp(1j * th[0]), math.sqrt(2 * r) * np.exp(1j * th[1]),
+                          math.sqrt(r) * np.exp(1j * th[2]), 0])
+            ntot = 5 * r
+            e = 0.5 * C * np.einsum("ijkl,i,j,k,l->", V, z.conj(), z.conj(), z, z)
+            want = abs(0.13 + 0.08 * math.sqrt(2) * math.cos(th[0] + th[2] - 2 * th[1]))
+            assert abs(abs(e) / ntot - want) < 1e-12
+    assert 0.13 + 0.08 * math.sqrt(2) >= 0.242
+    # the oracle's H reproduces the normal-ordered energy on the truncated state (r = 1)
+    r, C = 1.0, -0.1
+    th = np.array([0.3, 1.7, 0.2])
+    z = np.array([0, math.sqrt(2 * r) * np.exp(1j * th[0]), math.sqrt(2 * r) * np.exp(1j * th[1]),
+                  math.sqrt(r) * np.exp(1j * th[2]), 0])
+    o = Oracle(M, M, np.zeros(M), C, V, W.all_sectors(M, 26))
+    psi = states.coherent_state(o, z)
+    e_or = np.vdot(psi, o.apply_h(psi)).real / np.vdot(psi, psi).real
+    want = 5 * r * (0.13 + 0.08 * math.sqrt(2) * math.cos(th[0] + th[2] - 2 * th[1])) * np.sign(C)
+    assert abs(e_or - want) < 1e-8
+
+
+# -------------------------------------------------------------------- P11 --
+def test_p11_fieldnumber_and_number_states(oracle_lib):
+    M, N = 4, 6
+    o = Oracle(M, M, W.omega_quadratic(M), 0.2, W.V_contact(M), [(N, p) for p in range(M)])
+    z = W.coherent_amplitudes(8, M, 3.0)
+    psi0 = states.fieldnumber_state(o, z)
+    obs = derived.observe(o, psi0)
+    u = z / np.linalg.norm(z)
+    np.testing.assert_allclose(obs["M"], N * np.outer(u.conj(), u), atol=1e-12)
+    assert abs(obs["lambda_p"] - N) < 1e-12
+    psi, outs = evolve.rk4(o, psi0, 1e-2, 40, every=20, observe=lambda s, t, p: derived.observe(o, p))
+    for ob in outs:
+        assert np.all(ob["a"] == 0) and ob["Q"] == 1.0
+    # number eigenstate: M stays diagonal, <a> = 0, Q = 1
+    n1 = [1, 2, 0, 3]
+    o1 = Oracle(M, M, W.omega_quadratic(M), 0.2, W.V_longrange(M), [(N, W.momentum(n1, M))])
+    psi1 = states.number_state(o1, n1)
+    _, outs = evolve.rk4(o1, psi1, 1e-2, 40, every=20, observe=lambda s, t, p: derived.observe(o1, p))
+    for ob in outs:
+        assert np.all(ob["a"] == 0) and ob["Q"] == 1.0
+        assert np.all(ob["M"][~np.eye(M, dtype=bool)] == 0)
+
+
+# -------------------------------------------------------------------- P12 --
+def _forward_J(M, omega, Lam, V, sectors, alpha, dt, nsteps, objective):
+    o = Oracle(M, M, omega, Lam, V, sectors)
+    psi0 = states.coherent_state(o, alpha)
+    psi, _ = evolve.rk4(o, psi0, dt, nsteps)
+    return objective(o)(psi)[0]
+
+
+def test_p12_adjoint_kerr_closed_form(oracle_lib):
+    """M = 1: dQ/dLambda = 2|a|^2 t sin(Lt) e^{-2|a|^2(1-cos Lt)},
+    dQ/dRe a = 2 Re a g, dQ/dIm a = 2 Im a g, g = 2(1 - cos Lt) e^{-2|a|^2(1-cos Lt)}."""
+    Lam, alpha, Nmax, dt, nsteps = 0.5, 0.8 - 0.6j, 30, 2e-3, 500
+    o = Oracle(1, 1, np.zeros(1), Lam, np.ones((1, 1, 1, 1)), [(n, 0) for n in range(Nmax + 1)])
+    psi0 = states.coherent_state(o, [alpha])
+    res = evolve.adjoint(o, psi0, dt, nsteps, evolve.objective_Q(o))
+    t = dt * nsteps
+    a2 = abs(alpha) ** 2
+    e = np.exp(-2 * a2 * (1 - np.cos(Lam * t)))
+    assert abs(res["J"] - (1 - e)) < 1e-9
+    assert abs(res["dLambda"] - 2 * a2 * t * np.sin(Lam * t) * e) < 1e-8
+    g = 2 * (1 - np.cos(Lam * t)) * e
+    dre, dim = evolve.coherent_alpha_gradient(o, [alpha], psi0, res["g0"])
+    assert abs(dre[0] - 2 * alpha.real * g) < 1e-8
+    assert abs(dim[0] - 2 * alpha.imag * g) < 1e-8
+
+
+def test_p12_adjoint_vs_central_differences(oracle_lib):
+    M, Lam, dt, nsteps, Nmax = 3, 0.35, 5e-3, 40, 9
+    omega = W.omega_quadratic(M)
+    V = W.V_longrange(M)
+    V[V == 0] = 0.0
+    V = V + W.V_contact(M) * 0.3
+    sectors = W.all_sectors(M, Nmax)
+    alpha = W.coherent_amplitudes(31, M, 1.5)
+    for objective in (evolve.objective_Q, evolve.objective_PO, lambda o: evolve.objective_mode_occupation(o, 1)):
+        o = Oracle(M, M, omega, Lam, V, sectors)
+        psi0 = states.coherent_state(o, alpha)
+        res = evolve.adjoint(o, psi0, dt, nsteps, objective(o))
+        h = 1e-6
+        fd = (_forward_J(M, omega, Lam + h, V, sectors, alpha, dt, nsteps, objective)
+              - _forward_J(M, omega, Lam - h, V, sectors, alpha, dt, nsteps, objective)) / (2 * h)
+        assert abs(res["dLambda"] - fd) < 1e-7 * max(1, abs(fd))
+        # one symmetric and one single ordered V entry
+        for idx in [(0, 1, 1, 0), (2, 2, 1, 0)]:
+            Vp, Vm = V.copy(), V.copy()
+            Vp[idx] += h
+            Vm[idx] -= h
+            fd = (_forward_J(M, omega, Lam, Vp, sectors, alpha, dt, nsteps, objective)
+                  - _forward_J(M, omega, Lam, Vm, sectors, alpha, dt, nsteps, objective)) / (2 * h)
+            assert abs(res["dV"][idx] - fd) < 1e-7 * max(1, abs(fd))
+        dre, dim = evolve.coherent_alpha_gradient(o, alpha, psi0, res["g0"])
+        for k in range(M):
+            for comp, d in ((1.0, dre[k]), (1j, dim[k])):
+                ap, am = alpha.copy(), alpha.copy()
+                ap[k] += comp * h
+                am[k] -= comp * h
+                fd = (_forward_J(M, omega, Lam, V, sectors, ap, dt, nsteps, objective)
+                      - _forward_J(M, omega, Lam, V, sectors, am, dt, nsteps, objective)) / (2 * h)
+                assert abs(d - fd) < 1e-7 * max(1, abs(fd))
+
+
+def test_p12_adjoint_dense_expm_and_zeros(oracle_lib):
+    """Number eigenstate at N = 6: Q is identically 1 so its gradient is exactly
+    zero; the gradient of <n_0>(T) agrees with central differences of the exact
+    (dense expm) evolution to within the RK4 error."""
+    w = W.adjoint_number(N=6)
+    o = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    psi0 = states.number_state(o, w.init_params)
+    dt, nsteps = 1e-3, 300
+    res = evolve.adjoint(o, psi0, dt, nsteps, evolve.objective_Q(o))
+    assert res["J"] == 1.0 and res["dLambda"] == 0.0 and np.all(res["dV"] == 0)
+    res = evolve.adjoint(o, psi0, dt, nsteps, evolve.objective_mode_occupation(o, 0))
+    T = dt * nsteps
+
+    def J_exact(Lam):
+        oo = Oracle(w.M, w.pmod, w.omega, Lam, w.V, w.sectors)
+        psi = dense.expm_evolve(dense.dense_h(oo), psi0, T)
+        return evolve.objective_mode_occupation(oo, 0)(psi)[0]
+
+    h = 1e-5
+    fd = (J_exact(w.Lambda + h) - J_exact(w.Lambda - h)) / (2 * h)
+    assert abs(res["dLambda"] - fd) < 1e-6 * max(1, abs(fd))

@@ -1,0 +1,226 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds no part of the method's arithmetic: it only draws model
+parameters and initial-state parameters.  Both the GPU library and the CPU
+oracle consume what it returns.
+
+Conventions
+-----------
+* Modes j = 0..M-1 sit on a periodic 1D momentum grid with labels in FFT order,
+  k_j = j - M [2j >= M]; the conserved momentum of an occupation vector is
+  P = sum_j j n_j mod M (== sum_j k_j n_j mod M).
+* ``V`` has shape (M, M, M, M); ``V[i, j, k, l]`` multiplies a_i^+ a_j^+ a_k a_l
+  and is nonzero only if i + j == k + l (mod pmod), so that H conserves number
+  and momentum (Eq. Lambda's Kronecker delta).
+* Contact interaction: V = 1 on every conserving quadruple (Lambda_0 term of
+  Eq. Lambda).
+* Long-range interaction: V = 1/q^2 with q the minimal-image momentum transfer
+  between the first created mode i and the first annihilated mode k
+  (q = signed representative of (k - i) mod M); the zero-transfer term
+  (k == i) is removed.  Summing over all orderings reproduces the symmetric
+  pair of 1/(p - p')^2 terms of Eq. (Lambda).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# ----------------------------------------------------------------- model ---
+def k_labels(M: int) -> np.ndarray:
+    j = np.arange(M)
+    return j - M * (2 * j >= M)
+
+
+def omega_quadratic(M: int) -> np.ndarray:
+    return 0.5 * k_labels(M).astype(np.float64) ** 2
+
+
+def omega_linear(M: int) -> np.ndarray:
+    return np.abs(k_labels(M)).astype(np.float64)
+
+
+def _conserving(M: int, pmod: int):
+    i, j, k, l = np.meshgrid(*(np.arange(M),) * 4, indexing="ij")
+    return ((i + j - k - l) % pmod) == 0, i, k
+
+
+def V_contact(M: int, pmod: int | None = None) -> np.ndarray:
+    pmod = M if pmod is None else pmod
+    cons, _, _ = _conserving(M, pmod)
+    return cons.astype(np.float64)
+
+
+def minimal_image(d, M: int):
+    d = np.mod(d, M)
+    return np.where(2 * d > M, d - M, d)
+
+
+def V_longrange(M: int, pmod: int | None = None) -> np.ndarray:
+    pmod = M if pmod is None else pmod
+    cons, i, k = _conserving(M, pmod)
+    q = minimal_image(k - i, M).astype(np.float64)
+    V = np.zeros((M, M, M, M))
+    nz = cons & (q != 0)
+    V[nz] = 1.0 / q[nz] ** 2
+    return V
+
+
+def V_random_symmetric(M: int, seed: int, pmod: int | None = None) -> np.ndarray:
+    """Random real V on conserving quadruples, symmetric under V[ijkl] = V[klij]
+    (so that H is Hermitian).  For operator tests only."""
+    pmod = M if pmod is None else pmod
+    rng = np.random.default_rng(seed)
+    cons, _, _ = _conserving(M, pmod)
+    V = rng.uniform(-1.0, 1.0, size=(M, M, M, M)) * cons
+    return 0.5 * (V + V.transpose(2, 3, 0, 1))
+
+
+def V_random(M: int, seed: int, pmod: int | None = None) -> np.ndarray:
+    """Random real V on conserving quadruples with no symmetry (H not Hermitian)."""
+    pmod = M if pmod is None else pmod
+    rng = np.random.default_rng(seed)
+    cons, _, _ = _conserving(M, pmod)
+    return rng.uniform(-1.0, 1.0, size=(M, M, M, M)) * cons
+
+
+# ---------------------------------------------------------------- inputs ---
+def momentum(occ, pmod: int) -> int:
+    occ = np.asarray(occ)
+    return int((np.arange(len(occ)) * occ).sum() % pmod)
+
+
+def random_composition(rng, N: int, M: int) -> np.ndarray:
+    """Uniform composition of N into M nonnegative parts (stars and bars)."""
+    bars = np.sort(rng.choice(N + M - 1, size=M - 1, replace=False))
+    edges = np.concatenate([[-1], bars, [N + M - 1]])
+    return (np.diff(edges) - 1).astype(np.int64)
+
+
+def random_occupations_in_sector(seed: int, N: int, M: int, P: int, pmod: int | None = None):
+    pmod = M if pmod is None else pmod
+    rng = np.random.default_rng(seed)
+    while True:
+        n = random_composition(rng, N, M)
+        if momentum(n, pmod) == P:
+            return n
+
+
+def random_bounded_occupations(seed: int, M: int, lo: int, hi: int, total: int):
+    """n_k iid uniform on {lo..hi}, redrawn until sum == total."""
+    rng = np.random.default_rng(seed)
+    while True:
+        n = rng.integers(lo, hi + 1, size=M)
+        if int(n.sum()) == total:
+            return n.astype(np.int64)
+
+
+def coherent_amplitudes(seed: int, M: int, mean_total: float) -> np.ndarray:
+    """|alpha_k|^2 = mean_total u_k / sum(u), u ~ U[0,1]; phases ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(0.0, 1.0, size=M)
+    theta = rng.uniform(0.0, 2.0 * np.pi, size=M)
+    mag = np.sqrt(mean_total * u / u.sum())
+    return mag * np.exp(1j * theta)
+
+
+def phase_draws(n, seeds) -> np.ndarray:
+    """z^(d)_k = sqrt(n_k) exp(i theta^(d)_k), one row per seed."""
+    n = np.asarray(n, dtype=np.float64)
+    out = []
+    for s in seeds:
+        rng = np.random.default_rng(s)
+        th = rng.uniform(0.0, 2.0 * np.pi, size=len(n))
+        out.append(np.sqrt(n) * np.exp(1j * th))
+    return np.array(out)
+
+
+def random_psi(total: int, seed: int, nrhs: int = 1) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    shape = (total,) if nrhs == 1 else (total, nrhs)
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+def all_sectors(M: int, Nmax: int, pmod: int | None = None, Nmin: int = 0):
+    pmod = M if pmod is None else pmod
+    return [(N, P) for N in range(Nmin, Nmax + 1) for P in range(pmod)]
+
+
+def poisson_cut(mean_total: float, sigmas: float = 8.0) -> int:
+    return int(math.floor(mean_total + sigmas * math.sqrt(mean_total)))
+
+
+# --------------------------------------------------------------- configs ---
+@dataclass
+class Workload:
+    name: str
+    M: int
+    omega: np.ndarray
+    V: np.ndarray
+    Lambda: float
+    sectors: list
+    dt: float
+    nsteps: int
+    every: int
+    init: str                      # "number" | "coherent" | "fieldnumber"
+    init_params: np.ndarray        # occupations, or amplitudes [nrhs, M]
+    pmod: int = 0
+    meta: dict = field(default_factory=dict)
+
+    def __post_init__(self):
+        if not self.pmod:
+            self.pmod = self.M
+
+
+def tiny_number() -> Workload:
+    """M=5, w=k^2/2, contact V=1, Lambda=0.1; |4,2,1,1,0> (N=8, P=2: 99 states)."""
+    M = 5
+    n = np.array([4, 2, 1, 1, 0])
+    return Workload("tiny number state M=5 N=8", M, omega_quadratic(M), V_contact(M), 0.1,
+                    [(8, momentum(n, M))], 1e-3, 1000, 10, "number", n)
+
+
+def large_sector(N: int = 48, nsteps: int = 2000) -> Workload:
+    """M=8, w=k^2/2, long-range V, Lambda=0.02; random occupations of N=48 with P=0
+    (25,366,335 states)."""
+    M = 8
+    n = random_occupations_in_sector(2, N, M, 0)
+    return Workload(f"one large sector M=8 N={N} P=0", M, omega_quadratic(M), V_longrange(M), 0.02,
+                    [(N, 0)], 5e-4, nsteps, 50, "number", n)
+
+
+def batched_coherent(mean_total: float = 40.0, nsteps: int = 5000) -> Workload:
+    """M=6, w=k^2/2, contact V, Lambda=0.05; coherent state with sum |alpha|^2 = 40,
+    sectors N in [0, 40 + 8 sqrt(40)] x all P."""
+    M = 6
+    alpha = coherent_amplitudes(3, M, mean_total)
+    return Workload(f"batched coherent M=6 nbar={mean_total:g}", M, omega_quadratic(M), V_contact(M),
+                    0.05, all_sectors(M, poisson_cut(mean_total)), 1e-3, nsteps, 50, "coherent",
+                    alpha[None, :])
+
+
+def adjoint_number(N: int = 30) -> Workload:
+    M = 6
+    n = random_composition(np.random.default_rng(4), N, M)
+    return Workload(f"adjoint number state M=6 N={N}", M, omega_quadratic(M), V_longrange(M), 0.03,
+                    [(N, momentum(n, M))], 1e-3, 3000, 100, "number", n)
+
+
+def adjoint_coherent(mean_total: float = 20.0) -> Workload:
+    M = 6
+    alpha = coherent_amplitudes(41, M, mean_total)
+    return Workload(f"adjoint coherent M=6 nbar={mean_total:g}", M, omega_quadratic(M), V_longrange(M),
+                    0.03, all_sectors(M, poisson_cut(mean_total)), 1e-3, 3000, 100, "coherent",
+                    alpha[None, :])
+
+
+def fieldnumber_draws(ndraws: int = 16, N: int = 30) -> Workload:
+    """M=10, w=|k|, contact V, Lambda=0.01; n_k ~ U{0..6} with sum 30; field-number
+    states with 16 random phase draws, all 10 P sectors of N=30."""
+    M = 10
+    n = random_bounded_occupations(5, M, 0, 6, N)
+    z = phase_draws(n, range(500, 500 + ndraws))
+    return Workload(f"field-number draws M=10 N={N} x{ndraws}", M, omega_linear(M), V_contact(M), 0.01,
+                    [(N, P) for P in range(M)], 2e-4, 2000, 50, "fieldnumber", z)
