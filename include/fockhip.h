@@ -1,0 +1,213 @@
+/*
+ * fockhip.h -- C ABI of the MI355X (gfx950) Fock-sector evolution library.
+ *
+ * Method: Eberhardt, Zamora, Kopp & Abel, "On the single classical field
+ * description of interacting scalar fields", arXiv:2111.00050.
+ *
+ *   H = sum_j omega_j a_j^+ a_j + (Lambda/2) sum_{ijkl} V[i][j][k][l] a_i^+ a_j^+ a_k a_l
+ *                                                     (Sec. II.A, Eq. Ham / Eq. Lambda)
+ *   d|phi>/dt = -i H |phi>                            (Sec. II.A; Sec. III.B, Eq. Schr)
+ *
+ * States are expanded in the occupation-number basis (Sec. II.B, Eq.
+ * numEigenstate).  H conserves particle number N = sum_j n_j and momentum
+ * P = sum_j j n_j (mod pmod), so the basis splits into independent "special
+ * Hilbert spaces" (Sec. III.B) -- here called sectors (N, P).  A state is the
+ * concatenation of the amplitude vectors of a chosen list of sectors.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Modes j = 0..M-1 (1 <= M <= 10 on the GPU path); pmod must equal M
+ *    (periodic momentum grid).  Occupations are uint8 (N <= 255).
+ *  - Inside a sector, basis states are ordered lexicographically ascending
+ *    with n_0 the most significant entry; a state's index in that order is its
+ *    rank.  State vectors concatenate sectors in the order given to
+ *    fh_basis_create; fh_basis_sizes returns each sector's dimension and
+ *    offset.
+ *  - Amplitudes are complex FP64 (fh_c64, the layout of torch.complex128).
+ *    With nrhs > 1 right-hand sides the layout is [state][rhs], rhs fastest.
+ *  - Device pointers are HIP device memory owned by the caller (e.g. torch
+ *    tensors); host pointers are plain host memory, copied before return.
+ *  - 'stream' is a hipStream_t (NULL = the default stream).  Device work is
+ *    enqueued on it; entry points that return host results synchronise it.
+ *  - Every entry point returns an fh_status; no C++ exception crosses the ABI.
+ *    On failure fh_last_error() returns a thread-local message.  Arguments
+ *    are validated before any device work is enqueued.
+ *  - Handles are immutable after creation.  Calls that reduce over states
+ *    (fh_moments, fh_evolve_rk4 with observables, fh_adjoint_rk4,
+ *    fh_coherent_vjp) use scratch owned by the fh_basis: such calls on one
+ *    basis must not overlap on different streams.
+ */
+#ifndef FOCKHIP_H
+#define FOCKHIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FH_OK = 0,
+    FH_EINVAL = -1,       /* invalid argument */
+    FH_ENOMEM = -2,       /* allocation failed / caller buffer too small */
+    FH_EOVERFLOW = -3,    /* a count or index exceeds the supported integer range */
+    FH_EHIP = -4,         /* a HIP runtime call failed */
+    FH_ESTATE = -5,       /* non-finite result (e.g. NaN observable) */
+    FH_EUNSUPPORTED = -6  /* valid request outside what this build implements */
+} fh_status;
+
+typedef struct { double re, im; } fh_c64;
+typedef struct fh_model fh_model;
+typedef struct fh_basis fh_basis;
+
+/* Thread-local description of the last non-OK status returned on this thread. */
+const char* fh_last_error(void);
+/* Library version, 100*major + minor. */
+int fh_version(void);
+
+/* ------------------------------------------------------------------ model --
+ * Eq. (Ham) with the interaction tensor of Eq. (Lambda) given entrywise:
+ * V[((i*M + j)*M + k)*M + l] multiplies a_i^+ a_j^+ a_k a_l; the sum runs over
+ * all ordered quadruples with prefactor Lambda/2.  Every nonzero entry must
+ * conserve momentum, (i + j - k - l) mod pmod == 0, else FH_EINVAL.  V need
+ * not be symmetric; H is Hermitian iff V[i][j][k][l] summed over the
+ * orderings of {i,j} and of {k,l} is symmetric under {i,j} <-> {k,l}.
+ * omega[M], V[M^4] are host arrays, copied. */
+fh_status fh_model_create(int M, int pmod, const double* omega, double Lambda, const double* V,
+                          fh_model** out);
+/* The model of H^T (== H^+ for real V): V'[i][j][k][l] = V[k][l][i][j]. */
+fh_status fh_model_transpose(const fh_model* m, fh_model** out);
+fh_status fh_model_destroy(fh_model* m);
+
+/* ------------------------------------------------------------------ basis --
+ * Sector list (N[s], P[s]), s < nsec, host arrays; duplicates are EINVAL.
+ * Empty sectors (dimension 0) are allowed.  Builds the counting tables of the
+ * lexicographic rank (Sec. III.B; sizes as in App. A) on the host with
+ * overflow checks (FH_EOVERFLOW if a sector exceeds 2^31-1 states) and
+ * uploads them. */
+fh_status fh_basis_create(int M, int pmod, int nsec, const int32_t* N, const int32_t* P,
+                          fh_basis** out);
+fh_status fh_basis_destroy(fh_basis* b);
+/* M, pmod, number of sectors, total states (any output pointer may be NULL). */
+fh_status fh_basis_info(const fh_basis* b, int* M, int* pmod, int* nsec, int64_t* total);
+/* dim[nsec], offset[nsec + 1] (host). */
+fh_status fh_basis_sizes(const fh_basis* b, int64_t* dim, int64_t* offset);
+/* Rank of count occupation vectors occ[count*M] (device, uint8) in sector
+ * sec -> idx[count] (device int64); -1 for vectors not in that sector.
+ * Bit-exact integer work. */
+fh_status fh_basis_rank(const fh_basis* b, int sec, int64_t count, const uint8_t* occ,
+                        int64_t* idx, void* stream);
+/* Inverse: idx[count] (device, each in [0, dim)) -> occ[count*M] (device). */
+fh_status fh_basis_unrank(const fh_basis* b, int sec, int64_t count, const int64_t* idx,
+                          uint8_t* occ, void* stream);
+/* Occupations of the whole state vector, occ[total*M] (device). */
+fh_status fh_basis_occupations(const fh_basis* b, uint8_t* occ, void* stream);
+
+/* --------------------------------------------------------- initial states --
+ * Sec. II.B.  psi is device memory of total*nrhs fh_c64.
+ *  number     : occ[M] (host) -> one basis vector (every rhs); EINVAL if the
+ *               vector lies in no retained sector.
+ *  coherent   : alpha[nrhs*M] (host), Eq. (coherentStates):
+ *               psi(n) = prod_k exp(-|a_k|^2/2) a_k^n_k / sqrt(n_k!), truncated to
+ *               the retained sectors without renormalisation.
+ *  fieldnumber: z[nrhs*M] (host), Eq. (fieldNumState) read as
+ *               psi(n) ~ prod_k z_k^n_k / sqrt(n_k!), normalised to 1 over the
+ *               retained sectors. */
+fh_status fh_init_number(const fh_basis* b, const uint8_t* occ, int nrhs, fh_c64* psi, void* stream);
+fh_status fh_init_coherent(const fh_basis* b, const fh_c64* alpha, int nrhs, fh_c64* psi, void* stream);
+fh_status fh_init_fieldnumber(const fh_basis* b, const fh_c64* z, int nrhs, fh_c64* psi, void* stream);
+
+/* ---------------------------------------------------------------- H apply --
+ * out = H psi on every sector (the projected Hamiltonians H^j of Sec. III.B,
+ * applied matrix-free).  psi, out: device, total*nrhs; must not alias.
+ * nrhs in {1, 2, 4, 8, 16}. */
+fh_status fh_apply_h(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi, fh_c64* out,
+                     void* stream);
+
+/* ---------------------------------------------------------- observables --
+ * Moments of one right-hand side (rhs < nrhs), unnormalised:
+ *   norm2 = <psi|psi>, a[i] = <psi|a_i|psi>, Mij[i*M+j] = <psi|a_i^+ a_j|psi>,
+ *   Akl[k*M+l] = <psi|a_k a_l|psi>   (host outputs; NULL to skip a group).
+ * Matrix elements into sectors that are not retained count as zero.
+ * Used by Eq. (Qparam), Eq. (POcriterion), Eq. (generalVminus). */
+fh_status fh_moments(const fh_basis* b, int nrhs, int rhs, const fh_c64* psi, double* norm2,
+                     fh_c64* a, fh_c64* Mij, fh_c64* Akl, void* stream);
+
+typedef struct {
+    double norm2;      /* <psi|psi> */
+    double n_tot;      /* sum_i <a_i^+ a_i> / norm2 */
+    double Q;          /* Eq. (Qparam) */
+    double lambda_p;   /* largest eigenvalue of M_ij / norm2 (Eq. POcriterion) */
+    double po_deficit; /* 1 - lambda_p / n_tot */
+    double vminus;     /* Eq. (generalVminus) for O = a^p of Eq. (a_op); NaN if the
+                          top eigenvalue is degenerate to 1e-8 relative */
+} fh_obs_scalars;
+/* Derived scalars from moments (host only; no device work).  xi[M] (may be
+ * NULL) receives the principal eigenvector; vminus_mode[M] (may be NULL) the
+ * per-mode V_- with O = a_i. */
+fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c64* Mij, const fh_c64* Akl,
+                    fh_obs_scalars* s, fh_c64* xi, double* vminus_mode);
+
+/* ----------------------------------------------------------------- evolve --
+ * nsteps classical RK4 steps of dt on d psi/dt = -i H psi, in place on psi
+ * (device, total*nrhs).  work: device scratch of 3*total*nrhs fh_c64.
+ * If obs_every > 0, moments of every rhs are taken at steps 0, obs_every,
+ * 2*obs_every, ... <= nsteps and written to 'moments' (host) as consecutive
+ * records of FH_MOMENT_DOUBLES(M) doubles per (record, rhs):
+ *   [norm2, a (2M), Mij (2M^2), Akl (2M^2)]   (complex as re, im pairs).
+ * moments_capacity is the number of doubles available there.
+ * flags: FH_PER_SECTOR launches every stage once per sector (the plain
+ *        per-sector method); default is one persistent launch per stage over
+ *        all sectors.  FH_GRAPH replays each step from a captured hipGraph.
+ *        FH_TIMING records HIP events around every stage launch (not
+ *        compatible with FH_GRAPH) and returns kernel time in *timing. */
+#define FH_PER_SECTOR 1
+#define FH_GRAPH 2
+#define FH_TIMING 4
+#define FH_MOMENT_DOUBLES(M) (1 + 2 * (M) + 4 * (M) * (M))
+typedef struct {
+    double stage_ms;        /* summed duration of the H psi stage launches */
+    int64_t stage_launches; /* number of such launches */
+    double wall_ms;         /* host wall time of the whole call */
+} fh_timing;
+fh_status fh_evolve_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work,
+                        double dt, int64_t nsteps, int64_t obs_every, double* moments,
+                        int64_t moments_capacity, int flags, fh_timing* timing, void* stream);
+
+/* Launch configuration of the stage kernel for this basis: persistent
+ * workgroups per compute unit (0 = occupancy limit) and the XCD-aware tile
+ * order (0 = plain round robin, 1 = contiguous tile ranges per XCD).
+ * Not thread-safe with concurrent calls on the same basis. */
+fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
+
+/* ---------------------------------------------------------------- adjoint --
+ * Discrete adjoint of nsteps RK4 steps from psi0 (device), for the objective
+ * J at t = nsteps*dt:
+ *   FH_J_Q      : Q of Eq. (Qparam)
+ *   FH_J_PO     : 1 - lambda_p / n_tot (Eq. POcriterion)
+ *   FH_J_NMODE  : <a_k^+ a_k> with k = obj_mode
+ * Checkpoints every ckpt_every steps.  work: device scratch of at least
+ * fh_adjoint_work_states(...) * total * nrhs fh_c64.  Outputs: lambda0
+ * (device, total*nrhs) = 2 dJ/d conj(psi0); J[nrhs], dJ_dLambda[nrhs],
+ * dJ_dV[nrhs*M^4] (host; dJ_dV may be NULL).  Each ordered, momentum-
+ * conserving V entry is an independent parameter; entries that do not conserve
+ * momentum are not parameters of the model (fh_model_create rejects them) and
+ * their dJ_dV is 0. */
+#define FH_J_Q 0
+#define FH_J_PO 1
+#define FH_J_NMODE 2
+int64_t fh_adjoint_work_states(int64_t nsteps, int64_t ckpt_every);
+fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi0, double dt,
+                         int64_t nsteps, int64_t ckpt_every, int objective, int obj_mode, fh_c64* work,
+                         int64_t work_states, fh_c64* lambda0, double* J, double* dJ_dLambda,
+                         double* dJ_dV, void* stream);
+/* Vector-Jacobian product of the coherent initial state (Eq. coherentStates):
+ * given lambda0 = 2 dJ/d conj(psi0) for psi0 = coherent(alpha), returns
+ * dJ/dRe(alpha)[nrhs*M] and dJ/dIm(alpha)[nrhs*M] (host). */
+fh_status fh_coherent_vjp(const fh_basis* b, int nrhs, const fh_c64* alpha, const fh_c64* lambda0,
+                          double* d_re, double* d_im, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FOCKHIP_H */

@@ -1,0 +1,97 @@
+"""Build libfockhip.so in-tree with hipcc for gfx950.
+
+    python -m paper_2111_00050_amd.build            # compile every unit, link
+    python -m paper_2111_00050_amd.build --jobs 8
+
+Each mode count M = 1..10 has its own translation unit (inst.hip with
+-DFH_INST_M=M) so that the large, fully unrolled kernels compile in parallel.
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import os
+import shutil
+import subprocess
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "libfockhip.so")
+ARCH = os.environ.get("FH_OFFLOAD_ARCH", "gfx950")
+MODES = list(range(1, 11))
+
+COMMON = [
+    "-O3",
+    "-std=c++20",
+    f"--offload-arch={ARCH}",
+    "-fPIC",
+    # keep the compiler from forming packed FP32 instructions
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+]
+
+
+def hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _units():
+    units = []
+    for m in MODES:
+        units.append((os.path.join(CSRC, "inst.hip"), os.path.join(OBJ, f"inst_M{m}.o"), [f"-DFH_INST_M={m}"]))
+    for f in ("util.hip", "api.hip", "derive.cpp"):
+        src = os.path.join(CSRC, f)
+        extra = ["-x", "hip"] if f.endswith(".cpp") else []
+        units.append((src, os.path.join(OBJ, os.path.splitext(f)[0] + ".o"), extra))
+    return units
+
+
+def _compile(cc, src, obj, extra):
+    cmd = [cc, *COMMON, *extra, "-c", src, "-o", obj]
+    t0 = time.time()
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    msgs = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if "packed-fp32-ops" not in l)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{msgs}")
+    return obj, time.time() - t0, msgs
+
+
+def build(jobs: int | None = None, verbose: bool = True) -> str:
+    cc = hipcc()
+    os.makedirs(OBJ, exist_ok=True)
+    jobs = jobs or max(1, min(8, os.cpu_count() or 1))
+    units = _units()
+    # longest units (large M) first
+    units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] and u[2][0].startswith("-DFH_INST_M") else 0)
+    t0 = time.time()
+    with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+        futs = [ex.submit(_compile, cc, *u) for u in units]
+        for f in cf.as_completed(futs):
+            obj, dt, msgs = f.result()
+            if verbose:
+                print(f"[build] {os.path.basename(obj)} {dt:.1f}s", flush=True)
+                if msgs.strip():
+                    print(msgs, flush=True)
+    tmp = LIB + ".tmp"
+    cmd = [cc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *[u[1] for u in units]]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, LIB)
+    if verbose:
+        print(f"[build] {LIB} in {time.time() - t0:.1f}s", flush=True)
+    return LIB
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--jobs", type=int, default=None)
+    a = ap.parse_args()
+    build(a.jobs)
+    sys.exit(0)

@@ -1,0 +1,239 @@
+// fh_common.hpp -- definitions shared by the host code and the gfx950 kernels.
+//
+// Notation (Sec. II.A, Eq. Ham; Sec. III.B):
+//   modes j = 0..M-1, momentum modulus p = M, sector (N, P) = all occupation
+//   vectors n with sum n_j = N and sum j n_j == P (mod M).
+//
+// Pairs.  An unordered mode pair {i, j} (i <= j) is indexed in the order
+// (0,0), (0,1), ..., (0,M-1), (1,1), ...  Its class is (i + j) mod M.  The
+// interaction a_i^+ a_j^+ a_k a_l conserves momentum iff {i,j} and {k,l} share
+// a class, and two different pairs of one class are disjoint, so a nonzero
+// off-diagonal matrix element <n| a_i^+ a_j^+ a_k a_l |n'> links
+//   n' = n - e_i - e_j + e_k + e_l      ("row pair" {i,j}, "source pair" {k,l})
+// and the pair of pairs is unique for every neighbour n' of n.
+//
+// Combinations.  The off-diagonal combinations are the ordered pairs
+// (row pair, source pair) of distinct pairs in one class, enumerated with the
+// row pair outermost, both in pair order.  Host and device share this
+// enumeration (the coefficient table is laid out in it).
+#pragma once
+#include <cstdint>
+
+#ifndef __HIPCC__
+#define FH_HD
+#else
+#define FH_HD __host__ __device__
+#endif
+
+namespace fh {
+
+constexpr int kMaxM = 10;
+constexpr int kTileRows = 256;  // one row per thread, four wave64s per workgroup
+constexpr int kRBias = 2;       // rank table rows R = -2 .. Nmax+2
+
+template <int M>
+struct PairTable {
+    static constexpr int NP = M * (M + 1) / 2;
+    int i[NP];
+    int j[NP];
+    constexpr PairTable() : i{}, j{} {
+        int c = 0;
+        for (int a = 0; a < M; ++a)
+            for (int b = a; b < M; ++b) {
+                i[c] = a;
+                j[c] = b;
+                ++c;
+            }
+    }
+};
+
+template <int M>
+struct Combos {
+    static constexpr int NP = M * (M + 1) / 2;
+    static constexpr PairTable<M> pairs{};
+    static constexpr int cls(int p) { return (pairs.i[p] + pairs.j[p]) % M; }
+    static constexpr bool linked(int p1, int p2) { return p1 != p2 && cls(p1) == cls(p2); }
+    static constexpr int count() {
+        int c = 0;
+        for (int p1 = 0; p1 < NP; ++p1)
+            for (int p2 = 0; p2 < NP; ++p2)
+                if (linked(p1, p2)) ++c;
+        return c;
+    }
+    static constexpr int NC = count();
+    static constexpr int index(int p1, int p2) {
+        int c = 0;
+        for (int q1 = 0; q1 < NP; ++q1)
+            for (int q2 = 0; q2 < NP; ++q2)
+                if (linked(q1, q2)) {
+                    if (q1 == p1 && q2 == p2) return c;
+                    ++c;
+                }
+        return -1;
+    }
+    // pairs of class c, in pair order
+    static constexpr int class_size(int c) {
+        int n = 0;
+        for (int p = 0; p < NP; ++p)
+            if (cls(p) == c) ++n;
+        return n;
+    }
+    static constexpr int class_member(int c, int r) {
+        int n = 0;
+        for (int p = 0; p < NP; ++p)
+            if (cls(p) == c) {
+                if (n == r) return p;
+                ++n;
+            }
+        return -1;
+    }
+    static constexpr int max_class_size() {
+        int m = 0;
+        for (int c = 0; c < M; ++c)
+            if (class_size(c) > m) m = class_size(c);
+        return m;
+    }
+};
+
+// Runtime (host) versions of the same enumeration.
+inline int n_pairs(int M) { return M * (M + 1) / 2; }
+
+struct SecInfo {
+    int N, P, dim, pad;
+    long long off;
+};
+
+struct Tile {
+    int sec, row0, nrows, pad;
+};
+
+// Epilogue of the fused stage kernel.  With h = (H x)(row) and k = ks * h:
+//   APPLY : out      = h
+//   FIRST : acc      = base + a k ;  ynext = c0 base + b k
+//   MID   : acc      = acc  + a k ;  ynext = c0 base + b k
+//   LAST  : baseout  = acc  + a k
+enum StageMode { kApply = 0, kFirst = 1, kMid = 2, kLast = 3 };
+
+struct StageArgs {
+    const double* x;      // gathered vector, complex interleaved
+    double* out;
+    const double* base;
+    double* acc;
+    double* ynext;
+    double* baseout;
+    double ks_re, ks_im;
+    double a, c0, b;
+    int mode;
+    const int* T;         // rank table (ints)
+    int Tn;               // number of ints
+    int Rdim;             // Nmax + 5
+    const double* coef;   // omega[M] | Wd[NP] | W[NC]
+    int ncoef;
+    const double* sqrt_tab;  // sqrt(0..Nmax+2)
+    int nsqrt;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    int xcd_order;
+};
+
+// Moments / one-body kernels.
+struct MomArgs {
+    const double* psi;
+    int nrhs, rhs;
+    const int* T;
+    int Tn, Rdim;
+    const double* sqrt_tab;
+    int nsqrt;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    const int* secmap;  // [(N) * M + P] -> sector id or -1, N in [0, Nmax]
+    int Nmax;
+    double* partial;    // [group][grid][kMomOut] complex
+    int xcd_order;
+};
+constexpr int momentsOut(int M) { return 2 * M + 1; }
+// LDS layout of the table-staging kernels: rank table (ints, padded to an even
+// count), then the sqrt table (doubles), then reduction space.
+FH_HD constexpr int lds_sqrt_offset(int Tn) { return (Tn + 1) & ~1; }
+constexpr int kMomOutMax = 2 * kMaxM + 1;
+
+// One-body source  g(n) = c0 x(n) + cN N(n) x(n) + sum_i u_i (a_i x)(n)
+//                        + sum_i v_i (a_i^+ x)(n) + sum_ij h_ij (a_i^+ a_j x)(n)
+struct OneBodyArgs {
+    const double* psi;
+    double* out;
+    int nrhs, rhs;
+    const int* T;
+    int Tn, Rdim;
+    const double* sqrt_tab;
+    int nsqrt;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    const int* secmap;
+    int Nmax;
+    const double* cf;   // c0(2), cN(2), u[M](2), v[M](2), h[M*M](2)
+};
+
+// Quartic correlators  G[c][(p1,p2)] = sum_n conj(u(n)) <n|a_i^+ a_j^+ a_k a_l|n'> y(n')
+// for pairs p1 = {i,j}, p2 = {k,l} of class c (p1 == p2 included).
+struct CorrArgs {
+    const double* u;
+    const double* y;
+    double uscale;      // u is used as uscale * u
+    int nrhs, rhs;
+    const int* T;
+    int Tn, Rdim;
+    const double* sqrt_tab;
+    int nsqrt;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    double* partial;    // [class][grid][kCorrOutMax] complex
+    int xcd_order;
+};
+constexpr int kCorrOutMax = 36;  // (max class size)^2 for M <= 10
+
+// Initial states.
+struct InitArgs {
+    double* psi;
+    int nrhs;
+    const int* T;
+    int Tn, Rdim;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    const double* tab;  // [rhs][M][Nmax+1] complex: per-mode factors
+    int Nmax;
+};
+
+// Coherent-state vector-Jacobian product: per rhs, sums
+//   S0 = sum conj(g) psi0,  S_k = sum conj(g) psi0 with factor k replaced by tabd.
+struct VjpArgs {
+    const double* g;
+    int nrhs, rhs;
+    const int* T;
+    int Tn, Rdim;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    const double* tab;   // [M][Nmax+1] complex factors of psi0 (this rhs)
+    const double* tabd;  // [M][Nmax+1] complex factors n a^(n-1)/sqrt(n!) e^{-|a|^2/2}
+    int Nmax;
+    double* partial;     // [grid][kMaxM+1] complex
+};
+
+struct RankArgs {
+    const uint8_t* occ;
+    const int64_t* idx_in;
+    int64_t* idx;
+    uint8_t* occ_out;
+    long long count;
+    int N, P, dim;
+    const int* T;
+    int Tn, Rdim;
+};
+
+}  // namespace fh

@@ -1,0 +1,661 @@
+// fh_device.hpp -- gfx950 kernels, templated on the number of modes M.
+//
+// Lexicographic rank (Sec. III.B sectors; sizes as in App. A).
+// Let D_m(R, Q) count occupation vectors of modes m..M-1 with sum R and
+// momentum sum_{j>=m} j n_j == Q (mod M).  The lexicographic rank of n inside
+// its sector (N, P) (n_0 most significant) telescopes into
+//     rank(n) = D_0(N, P) - 1 - sum_{s=1}^{M-1} T_s(R_s, Q_s),
+//     T_s(R, Q) = D_{s-1}(R - 1, Q - (s - 1))   (0 for R <= 0),
+// where (R_s, Q_s) are the suffix sums of n from mode s on.  T_s(R_s, Q_s)
+// counts the sector states that agree with n on modes < s-1 and hold more
+// bosons in mode s-1.  A neighbour n' that differs from n only in modes
+// a..d changes (R_s, Q_s) only for a < s <= d, so its rank costs d - a table
+// reads from the row's own terms.  The table (one int per (s, R, Q), with Q
+// stored twice so that Q + dQ needs no reduction and R biased by two) lives in
+// LDS; every offset (dR, dQ) of a neighbour is a compile-time constant folded
+// into the ds_read immediate.
+//
+// H psi (Eq. Ham, projected on each sector as in Sec. III.B), gather form:
+//   (H x)(n) = [sum_j w_j n_j + sum_{pairs} Wd_p occ_p(n)] x(n)
+//            + sum_{row pair {i,j}} c_ij(n) sum_{source pair {k,l} of the class}
+//                  W_{ij,kl} c_kl(n) x(n - e_i - e_j + e_k + e_l),
+//   c_ij = sqrt(n_i (n_j - d_ij)), c_kl = sqrt((n_k + 1)(n_l + 1 + d_kl)),
+//   W_{ij,kl} = (Lambda/2) sum over the orderings of both pairs of V.
+// One thread owns one row; a workgroup owns a tile of 256 consecutive rows of
+// one sector; workgroups are persistent and stride over the tile list.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+#include <utility>
+
+#include "fh_common.hpp"
+
+namespace fh {
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+__device__ __forceinline__ int virtual_block(int xcd_order) {
+    const int b = blockIdx.x, G = gridDim.x;
+    // Workgroups are dealt to the 8 XCDs round robin; map each XCD to a
+    // contiguous range of virtual ids so that its L2 sees neighbouring tiles.
+    if (xcd_order && (G & 7) == 0) return (b & 7) * (G >> 3) + (b >> 3);
+    return b;
+}
+
+template <int M>
+__device__ __forceinline__ int modM(int x) {
+    x %= M;
+    return x < 0 ? x + M : x;
+}
+
+template <int M>
+constexpr int cmod(int x) {
+    return ((x % M) + M) % M;
+}
+
+// Table offset of T_s(R_s + dR, Q_s + dQ) relative to the row's key for mode
+// s, for a move that adds the modes in 'add' and removes those in 'rem'
+// (entries -1 are unused).
+template <int M>
+constexpr int move_offset(int s, int add0, int add1, int rem0, int rem1) {
+    int dR = 0, dQ = 0;
+    if (add0 >= 0 && add0 >= s) { dR += 1; dQ += add0; }
+    if (add1 >= 0 && add1 >= s) { dR += 1; dQ += add1; }
+    if (rem0 >= 0 && rem0 >= s) { dR -= 1; dQ -= rem0; }
+    if (rem1 >= 0 && rem1 >= s) { dR -= 1; dQ -= rem1; }
+    return (dR + kRBias) * 2 * M + cmod<M>(dQ);
+}
+
+// Unrank row r of sector (N, P) with the table in LDS.
+//   D_{m+1}(R', Q') = T_{m+2}(R' + 1, Q' + m + 1)     for m + 1 <= M - 2
+//   D_{M-1}(R', Q') = [(M - 1) R' == Q' (mod M)]
+template <int M>
+__device__ __forceinline__ void unrank_row(const int* sT, int Rdim, int N, int P, int r, int (&n)[M]) {
+    constexpr int P2 = 2 * M;
+    int R = N, Q = P;
+#pragma unroll
+    for (int m = 0; m < M - 1; ++m) {
+        int v = 0;
+        while (v < R) {
+            const int q = modM<M>(Q - m * v);
+            int cnt;
+            if (m + 1 <= M - 2) {
+                cnt = sT[(m + 1) * Rdim * P2 + (R - v + 1 + kRBias) * P2 + modM<M>(q + m + 1)];
+            } else {
+                cnt = (modM<M>((M - 1) * (R - v)) == q) ? 1 : 0;
+            }
+            if (r < cnt) break;
+            r -= cnt;
+            ++v;
+        }
+        n[m] = v;
+        R -= v;
+        Q = modM<M>(Q - m * v);
+    }
+    n[M - 1] = R;
+}
+
+// key[s] (s >= 1): table index of T_s at the row's own suffix sums.
+// C[x] = sum_{s=1}^{x} T_s(R_s, Q_s), C[0] = 0.
+template <int M>
+__device__ __forceinline__ void row_keys(const int* sT, int Rdim, const int (&n)[M], int (&key)[M], int (&C)[M]) {
+    constexpr int P2 = 2 * M;
+    int Rs[M], Qs[M];
+    int R = 0, Q = 0;
+#pragma unroll
+    for (int s = M - 1; s >= 1; --s) {
+        R += n[s];
+        Q = modM<M>(Q + s * n[s]);
+        Rs[s] = R;
+        Qs[s] = Q;
+    }
+    C[0] = 0;
+    key[0] = 0;
+#pragma unroll
+    for (int s = 1; s < M; ++s) {
+        key[s] = (s - 1) * Rdim * P2 + Rs[s] * P2 + Qs[s];
+        C[s] = C[s - 1] + sT[key[s] + kRBias * P2];
+    }
+}
+
+// Rank of the neighbour n + e_add0 + e_add1 - e_rem0 - e_rem1 inside the
+// sector of dimension dim_dst, given the row's keys (modes lo..hi changed).
+template <int M, int LO, int HI, int A0, int A1, int R0, int R1>
+__device__ __forceinline__ int move_rank(const int* sT, const int (&key)[M], const int (&C)[M], int dim_dst) {
+    // rank' = dim' - 1 - [sum_{s<=LO} T'_s] - [sum_{LO<s<=HI} T'_s] - [sum_{s>HI} T_s]
+    int r = dim_dst - 1 - (C[M - 1] - C[HI]);
+    static_for<1, HI + 1>([&](auto S) {
+        constexpr int s = decltype(S)::value;
+        r -= sT[key[s] + move_offset<M>(s, A0, A1, R0, R1)];
+    });
+    return r;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum 'NV' per-thread values over the workgroup; thread 0 gets the result in
+// out[].  Uses red (>= 4*NV doubles of LDS).
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) red[wave * NV + q] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w * NV + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ void stage_tables(const int* T, int Tn, const double* sq, int nsq, int* sT, double* sSq) {
+    for (int q = threadIdx.x; q < Tn; q += blockDim.x) sT[q] = T[q];
+    for (int q = threadIdx.x; q < nsq; q += blockDim.x) sSq[q] = sq[q];
+    __syncthreads();
+}
+
+
+// ------------------------------------------------------------ H psi stage --
+template <int M, int NRHS>
+__global__ __launch_bounds__(kTileRows) void stage_kernel(StageArgs A) {
+    using CB = Combos<M>;
+    constexpr int NP = CB::NP;
+    extern __shared__ int smem[];
+    int* sT = smem;
+    double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
+    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+
+    const double* __restrict__ cf = A.coef;
+    const double2* __restrict__ X = reinterpret_cast<const double2*>(A.x);
+    const int vb = virtual_block(A.xcd_order);
+    for (int t = vb; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        int key[M], C[M];
+        row_keys<M>(sT, A.Rdim, n, key, C);
+        double sq[M], sqp[M];
+#pragma unroll
+        for (int s = 0; s < M; ++s) {
+            sq[s] = sSq[n[s]];
+            sqp[s] = sSq[n[s] + 1];
+        }
+        double diag = 0.0;
+#pragma unroll
+        for (int s = 0; s < M; ++s) diag = fma(cf[s], (double)n[s], diag);
+        static_for<0, NP>([&](auto Pc) {
+            constexpr int p = decltype(Pc)::value;
+            constexpr int i = CB::pairs.i[p], j = CB::pairs.j[p];
+            const double occ = (i == j) ? (double)(n[i] * (n[i] - 1)) : (double)(n[i] * n[j]);
+            diag = fma(cf[M + p], occ, diag);
+        });
+
+        const long long soff = sc.off;
+        const double2* __restrict__ xs = X + soff * NRHS;
+        double2 acc[NRHS];
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) acc[q] = make_double2(0.0, 0.0);
+
+        static_for<0, NP>([&](auto P1) {
+            constexpr int p1 = decltype(P1)::value;
+            constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+            if constexpr (CB::class_size(CB::cls(p1)) > 1) {
+                const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
+                if (valid) {
+                    const double cij = (i == j) ? sq[i] * sSq[n[i] - 1] : sq[i] * sq[j];
+                    double2 pacc[NRHS];
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) pacc[q] = make_double2(0.0, 0.0);
+                    static_for<0, NP>([&](auto P2) {
+                        constexpr int p2 = decltype(P2)::value;
+                        if constexpr (CB::linked(p1, p2)) {
+                            constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
+                            constexpr int c = CB::index(p1, p2);
+                            constexpr int lo = i < k ? i : k;
+                            constexpr int hi = j > l ? j : l;
+                            int r = row + (C[hi] - C[lo]);
+                            static_for<lo + 1, hi + 1>([&](auto S) {
+                                constexpr int s = decltype(S)::value;
+                                r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
+                            });
+                            const double ckl = (k == l) ? sqp[k] * sSq[n[k] + 2] : sqp[k] * sqp[l];
+                            const double w = cf[M + NP + c] * ckl;
+                            const double2* src = xs + (long long)r * NRHS;
+#pragma unroll
+                            for (int q = 0; q < NRHS; ++q) {
+                                const double2 v = src[q];
+                                pacc[q].x = fma(w, v.x, pacc[q].x);
+                                pacc[q].y = fma(w, v.y, pacc[q].y);
+                            }
+                        }
+                    });
+#pragma unroll
+                    for (int q = 0; q < NRHS; ++q) {
+                        acc[q].x = fma(cij, pacc[q].x, acc[q].x);
+                        acc[q].y = fma(cij, pacc[q].y, acc[q].y);
+                    }
+                }
+            }
+        });
+
+        const long long e = (soff + row) * NRHS;
+#pragma unroll
+        for (int q = 0; q < NRHS; ++q) {
+            const double2 xv = X[e + q];
+            double2 h;
+            h.x = fma(diag, xv.x, acc[q].x);
+            h.y = fma(diag, xv.y, acc[q].y);
+            if (A.mode == kApply) {
+                reinterpret_cast<double2*>(A.out)[e + q] = h;
+                continue;
+            }
+            double2 kk;
+            kk.x = A.ks_re * h.x - A.ks_im * h.y;
+            kk.y = A.ks_re * h.y + A.ks_im * h.x;
+            if (A.mode == kLast) {
+                const double2 ac = reinterpret_cast<const double2*>(A.acc)[e + q];
+                reinterpret_cast<double2*>(A.baseout)[e + q] = make_double2(fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y));
+                continue;
+            }
+            const double2 bs = reinterpret_cast<const double2*>(A.base)[e + q];
+            const double2 ac = (A.mode == kFirst) ? bs : reinterpret_cast<const double2*>(A.acc)[e + q];
+            reinterpret_cast<double2*>(A.acc)[e + q] = make_double2(fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y));
+            reinterpret_cast<double2*>(A.ynext)[e + q] =
+                make_double2(fma(A.b, kk.x, A.c0 * bs.x), fma(A.b, kk.y, A.c0 * bs.y));
+        }
+    }
+}
+
+// ---------------------------------------------------------------- moments --
+// group 0: [0] <psi|psi>, [1+i] <a_i>, [1+M+i] <a_i^+ a_i>
+// group 1+i: [j] <a_i^+ a_j> (j != i), [M+l] <a_i a_l> (l >= i)
+// Each term: sum_n conj(psi(n')) c psi(n) with n' the image of n.
+template <int M>
+__global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
+    constexpr int NO = momentsOut(M);
+    extern __shared__ int smem[];
+    int* sT = smem;
+    double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
+    double* red = sSq + A.nsqrt;
+    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+
+    const double2* __restrict__ X = reinterpret_cast<const double2*>(A.psi);
+    const int g = blockIdx.y;
+    const int nrhs = A.nrhs, rhs = A.rhs;
+    double acc[2 * NO];
+#pragma unroll
+    for (int q = 0; q < 2 * NO; ++q) acc[q] = 0.0;
+
+    auto add = [&](int slot, double2 y, double c, double2 x) {
+        // conj(y) * c * x
+        acc[2 * slot] = fma(c, y.x * x.x + y.y * x.y, acc[2 * slot]);
+        acc[2 * slot + 1] = fma(c, y.x * x.y - y.y * x.x, acc[2 * slot + 1]);
+    };
+
+    const int vb = virtual_block(A.xcd_order);
+    for (int t = vb; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        int key[M], C[M];
+        row_keys<M>(sT, A.Rdim, n, key, C);
+        const double2 x = X[(sc.off + row) * nrhs + rhs];
+        const int N = sc.N, P = sc.P;
+        if (g == 0) {
+            const double x2 = x.x * x.x + x.y * x.y;
+            acc[0] += x2;
+            static_for<0, M>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                acc[2 * (1 + M + i)] = fma((double)n[i], x2, acc[2 * (1 + M + i)]);
+                if (N >= 1 && n[i] >= 1) {
+                    const int sid = A.secmap[(N - 1) * M + modM<M>(P - i)];
+                    if (sid >= 0) {
+                        const SecInfo pd = A.secs[sid];
+                        const int r = move_rank<M, 0, i, -1, -1, i, -1>(sT, key, C, pd.dim);
+                        add(1 + i, X[(pd.off + r) * nrhs + rhs], sSq[n[i]], x);
+                    }
+                }
+            });
+        } else {
+            static_for<0, M>([&](auto I) {
+                constexpr int i = decltype(I)::value;
+                if (g == 1 + i) {
+                    // <a_i^+ a_j>: n' = n - e_j + e_i, c = sqrt(n_j (n_i + 1))
+                    static_for<0, M>([&](auto J) {
+                        constexpr int j = decltype(J)::value;
+                        if constexpr (j != i) {
+                            if (n[j] >= 1) {
+                                const int sid = A.secmap[N * M + modM<M>(P + i - j)];
+                                if (sid >= 0) {
+                                    const SecInfo pd = A.secs[sid];
+                                    constexpr int hi = i > j ? i : j;
+                                    const int r = move_rank<M, 0, hi, i, -1, j, -1>(sT, key, C, pd.dim);
+                                    add(j, X[(pd.off + r) * nrhs + rhs], sSq[n[j]] * sSq[n[i] + 1], x);
+                                }
+                            }
+                        }
+                    });
+                    // <a_i a_l>, l >= i: n' = n - e_i - e_l, c = sqrt(n_l (n_i - d_il))
+                    static_for<i, M>([&](auto L) {
+                        constexpr int l = decltype(L)::value;
+                        const bool ok = (l == i) ? (n[i] >= 2) : (n[i] >= 1 && n[l] >= 1);
+                        if (N >= 2 && ok) {
+                            const int sid = A.secmap[(N - 2) * M + modM<M>(P - i - l)];
+                            if (sid >= 0) {
+                                const SecInfo pd = A.secs[sid];
+                                const int r = move_rank<M, 0, l, -1, -1, i, l>(sT, key, C, pd.dim);
+                                const double c = (l == i) ? sSq[n[i]] * sSq[n[i] - 1] : sSq[n[l]] * sSq[n[i]];
+                                add(M + l, X[(pd.off + r) * nrhs + rhs], c, x);
+                            }
+                        }
+                    });
+                }
+            });
+        }
+    }
+    __shared__ double outv[2 * kMomOutMax];
+    block_sum<2 * NO>(acc, red, outv);
+    if (threadIdx.x < 2 * NO) {
+        A.partial[((size_t)g * gridDim.x + blockIdx.x) * 2 * kMomOutMax + threadIdx.x] = outv[threadIdx.x];
+    }
+}
+
+// ------------------------------------------------------- one-body source --
+template <int M>
+__global__ __launch_bounds__(kTileRows) void onebody_kernel(OneBodyArgs A) {
+    extern __shared__ int smem[];
+    int* sT = smem;
+    double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
+    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+    const double2* __restrict__ X = reinterpret_cast<const double2*>(A.psi);
+    const double* cf = A.cf;
+    const int nrhs = A.nrhs, rhs = A.rhs;
+    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        int key[M], C[M];
+        row_keys<M>(sT, A.Rdim, n, key, C);
+        const int N = sc.N, P = sc.P;
+        const double2 x = X[(sc.off + row) * nrhs + rhs];
+        double ox = 0.0, oy = 0.0;
+        auto cmul_add = [&](double cr, double ci, double s, double2 y) {
+            // (cr + i ci) * s * y
+            ox += s * (cr * y.x - ci * y.y);
+            oy += s * (cr * y.y + ci * y.x);
+        };
+        double nt = 0.0;
+#pragma unroll
+        for (int s = 0; s < M; ++s) nt += (double)n[s];
+        cmul_add(cf[0] + cf[2] * nt, cf[1] + cf[3] * nt, 1.0, x);
+        static_for<0, M>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            const double* u = cf + 4 + 2 * i;
+            const double* v = cf + 4 + 2 * M + 2 * i;
+            // (a_i x)(n) = sqrt(n_i + 1) x(n + e_i)
+            if (N + 1 <= A.Nmax) {
+                const int sid = A.secmap[(N + 1) * M + modM<M>(P + i)];
+                if (sid >= 0) {
+                    const SecInfo pd = A.secs[sid];
+                    const int r = move_rank<M, 0, i, i, -1, -1, -1>(sT, key, C, pd.dim);
+                    cmul_add(u[0], u[1], sSq[n[i] + 1], X[(pd.off + r) * nrhs + rhs]);
+                }
+            }
+            // (a_i^+ x)(n) = sqrt(n_i) x(n - e_i)
+            if (N >= 1 && n[i] >= 1) {
+                const int sid = A.secmap[(N - 1) * M + modM<M>(P - i)];
+                if (sid >= 0) {
+                    const SecInfo pd = A.secs[sid];
+                    const int r = move_rank<M, 0, i, -1, -1, i, -1>(sT, key, C, pd.dim);
+                    cmul_add(v[0], v[1], sSq[n[i]], X[(pd.off + r) * nrhs + rhs]);
+                }
+            }
+            static_for<0, M>([&](auto J) {
+                constexpr int j = decltype(J)::value;
+                const double* h = cf + 4 + 4 * M + 2 * (i * M + j);
+                if constexpr (i == j) {
+                    cmul_add(h[0], h[1], (double)n[i], x);
+                } else {
+                    // (a_i^+ a_j x)(n) = sqrt(n_i (n_j + 1)) x(n - e_i + e_j)
+                    if (n[i] >= 1) {
+                        const int sid = A.secmap[N * M + modM<M>(P - i + j)];
+                        if (sid >= 0) {
+                            const SecInfo pd = A.secs[sid];
+                            constexpr int hi = i > j ? i : j;
+                            const int r = move_rank<M, 0, hi, j, -1, i, -1>(sT, key, C, pd.dim);
+                            cmul_add(h[0], h[1], sSq[n[i]] * sSq[n[j] + 1], X[(pd.off + r) * nrhs + rhs]);
+                        }
+                    }
+                }
+            });
+        });
+        reinterpret_cast<double2*>(A.out)[(sc.off + row) * nrhs + rhs] = make_double2(ox, oy);
+    }
+}
+
+// ------------------------------------------------------- correlators -----
+// G[class][r1 * S + r2] += sum_n conj(uscale u(n)) <n| a_i^+ a_j^+ a_k a_l |n'> y(n')
+// p1 = member(class, r1) = {i,j}, p2 = member(class, r2) = {k,l},
+// n' = n - e_i - e_j + e_k + e_l.
+template <int M>
+__global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
+    using CB = Combos<M>;
+    constexpr int NP = CB::NP;
+    constexpr int SMAX = CB::max_class_size();
+    constexpr int NV = 2 * SMAX * SMAX;
+    extern __shared__ int smem[];
+    int* sT = smem;
+    double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
+    double* red = sSq + A.nsqrt;
+    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+    const double2* __restrict__ U = reinterpret_cast<const double2*>(A.u);
+    const double2* __restrict__ Y = reinterpret_cast<const double2*>(A.y);
+    const int nrhs = A.nrhs, rhs = A.rhs;
+    const int cls = blockIdx.y;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    const int vb = virtual_block(A.xcd_order);
+    for (int t = vb; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        int key[M], C[M];
+        row_keys<M>(sT, A.Rdim, n, key, C);
+        double2 u = U[(sc.off + row) * nrhs + rhs];
+        u.x *= A.uscale;
+        u.y *= A.uscale;
+        static_for<0, M>([&](auto Cc) {
+            constexpr int c = decltype(Cc)::value;
+            constexpr int S = CB::class_size(c);
+            if (cls == c) {
+                static_for<0, S>([&](auto R1) {
+                    constexpr int r1 = decltype(R1)::value;
+                    constexpr int p1 = CB::class_member(c, r1);
+                    constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+                    const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
+                    if (valid) {
+                        const double cij = (i == j) ? sSq[n[i]] * sSq[n[i] - 1] : sSq[n[i]] * sSq[n[j]];
+                        static_for<0, S>([&](auto R2) {
+                            constexpr int r2 = decltype(R2)::value;
+                            constexpr int p2 = CB::class_member(c, r2);
+                            constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
+                            double2 y;
+                            double cc;
+                            if constexpr (p1 == p2) {
+                                y = Y[(sc.off + row) * nrhs + rhs];
+                                cc = cij * cij;
+                            } else {
+                                constexpr int lo = i < k ? i : k;
+                                constexpr int hi = j > l ? j : l;
+                                int r = row + (C[hi] - C[lo]);
+                                static_for<lo + 1, hi + 1>([&](auto Sx) {
+                                    constexpr int s = decltype(Sx)::value;
+                                    r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
+                                });
+                                y = Y[(sc.off + r) * nrhs + rhs];
+                                cc = cij * ((k == l) ? sSq[n[k] + 1] * sSq[n[k] + 2] : sSq[n[k] + 1] * sSq[n[l] + 1]);
+                            }
+                            constexpr int o = 2 * (r1 * SMAX + r2);
+                            acc[o] = fma(cc, u.x * y.x + u.y * y.y, acc[o]);
+                            acc[o + 1] = fma(cc, u.x * y.y - u.y * y.x, acc[o + 1]);
+                        });
+                    }
+                });
+            }
+        });
+    }
+    __shared__ double outv[2 * kCorrOutMax];
+    block_sum<NV>(acc, red, outv);
+    if (threadIdx.x < NV) {
+        A.partial[((size_t)cls * gridDim.x + blockIdx.x) * 2 * kCorrOutMax + threadIdx.x] = outv[threadIdx.x];
+    }
+}
+
+// ------------------------------------------------------- initial states --
+template <int M>
+__global__ __launch_bounds__(kTileRows) void init_product_kernel(InitArgs A) {
+    extern __shared__ int smem[];
+    int* sT = smem;
+    for (int q = threadIdx.x; q < A.Tn; q += blockDim.x) sT[q] = A.T[q];
+    __syncthreads();
+    const double2* tab = reinterpret_cast<const double2*>(A.tab);
+    const int W = A.Nmax + 1;
+    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        for (int q = 0; q < A.nrhs; ++q) {
+            double2 p = tab[(size_t)(q * M + 0) * W + n[0]];
+#pragma unroll
+            for (int m = 1; m < M; ++m) {
+                const double2 f = tab[(size_t)(q * M + m) * W + n[m]];
+                p = make_double2(p.x * f.x - p.y * f.y, p.x * f.y + p.y * f.x);
+            }
+            reinterpret_cast<double2*>(A.psi)[(sc.off + row) * A.nrhs + q] = p;
+        }
+    }
+}
+
+// S0 = sum conj(g) psi0 ; S_k = sum conj(g) psi0^(k) (factor k from tabd)
+template <int M>
+__global__ __launch_bounds__(kTileRows) void vjp_kernel(VjpArgs A) {
+    constexpr int NV = 2 * (M + 1);
+    extern __shared__ int smem[];
+    int* sT = smem;
+    double* red = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
+    for (int q = threadIdx.x; q < A.Tn; q += blockDim.x) sT[q] = A.T[q];
+    __syncthreads();
+    const double2* tab = reinterpret_cast<const double2*>(A.tab);
+    const double2* tabd = reinterpret_cast<const double2*>(A.tabd);
+    const double2* G = reinterpret_cast<const double2*>(A.g);
+    const int W = A.Nmax + 1;
+    double acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        const double2 g = G[(sc.off + row) * A.nrhs + A.rhs];
+        double2 f[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m) f[m] = tab[(size_t)m * W + n[m]];
+#pragma unroll
+        for (int k = -1; k < M; ++k) {
+            double2 p = make_double2(1.0, 0.0);
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                const double2 fm = (m == k) ? tabd[(size_t)m * W + n[m]] : f[m];
+                p = make_double2(p.x * fm.x - p.y * fm.y, p.x * fm.y + p.y * fm.x);
+            }
+            // conj(g) p
+            acc[2 * (k + 1)] += g.x * p.x + g.y * p.y;
+            acc[2 * (k + 1) + 1] += g.x * p.y - g.y * p.x;
+        }
+    }
+    __shared__ double outv[2 * (kMaxM + 1)];
+    block_sum<NV>(acc, red, outv);
+    if (threadIdx.x < NV) A.partial[(size_t)blockIdx.x * 2 * (kMaxM + 1) + threadIdx.x] = outv[threadIdx.x];
+}
+
+// ------------------------------------------------------ rank / unrank -----
+template <int M>
+__global__ void rank_kernel(RankArgs A) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.count) return;
+    constexpr int P2 = 2 * M;
+    int n[M];
+    int N = 0, mom = 0;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        n[m] = A.occ[q * M + m];
+        N += n[m];
+        mom = modM<M>(mom + m * n[m]);
+    }
+    if (N != A.N || mom != A.P) {
+        A.idx[q] = -1;
+        return;
+    }
+    long long r = (long long)A.dim - 1;
+    int R = 0, Q = 0;
+#pragma unroll
+    for (int s = M - 1; s >= 1; --s) {
+        R += n[s];
+        Q = modM<M>(Q + s * n[s]);
+        r -= A.T[(s - 1) * A.Rdim * P2 + (R + kRBias) * P2 + Q];
+    }
+    A.idx[q] = r;
+}
+
+template <int M>
+__global__ void unrank_kernel(RankArgs A) {
+    const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= A.count) return;
+    const long long r = A.idx_in[q];
+    int n[M];
+    if (r < 0 || r >= A.dim) {
+#pragma unroll
+        for (int m = 0; m < M; ++m) A.occ_out[q * M + m] = 0xff;
+        return;
+    }
+    unrank_row<M>(A.T, A.Rdim, A.N, A.P, (int)r, n);
+#pragma unroll
+    for (int m = 0; m < M; ++m) A.occ_out[q * M + m] = (uint8_t)n[m];
+}
+
+}  // namespace fh

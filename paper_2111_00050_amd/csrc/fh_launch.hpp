@@ -1,0 +1,74 @@
+// fh_launch.hpp -- per-M kernel sets (one translation unit per M) and the
+// generic utility kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "fh_common.hpp"
+
+namespace fh {
+
+constexpr int kNrhsVariants = 5;  // nrhs = 1, 2, 4, 8, 16
+inline int nrhs_slot(int nrhs) {
+    switch (nrhs) {
+        case 1: return 0;
+        case 2: return 1;
+        case 4: return 2;
+        case 8: return 3;
+        case 16: return 4;
+        default: return -1;
+    }
+}
+
+struct KernelSet {
+    int M;
+    const void* stage_fn[kNrhsVariants];
+    void (*stage)(int slot, const StageArgs&, int grid, size_t lds, hipStream_t);
+    const void* moments_fn;
+    void (*moments)(const MomArgs&, int grid, int groups, size_t lds, hipStream_t);
+    const void* onebody_fn;
+    void (*onebody)(const OneBodyArgs&, int grid, size_t lds, hipStream_t);
+    const void* corr_fn;
+    void (*corr)(const CorrArgs&, int grid, int classes, size_t lds, hipStream_t);
+    void (*init_product)(const InitArgs&, int grid, size_t lds, hipStream_t);
+    void (*vjp)(const VjpArgs&, int grid, size_t lds, hipStream_t);
+    void (*rank)(const RankArgs&, hipStream_t);
+    void (*unrank)(const RankArgs&, hipStream_t);
+};
+
+const KernelSet* kernel_set_M1();
+const KernelSet* kernel_set_M2();
+const KernelSet* kernel_set_M3();
+const KernelSet* kernel_set_M4();
+const KernelSet* kernel_set_M5();
+const KernelSet* kernel_set_M6();
+const KernelSet* kernel_set_M7();
+const KernelSet* kernel_set_M8();
+const KernelSet* kernel_set_M9();
+const KernelSet* kernel_set_M10();
+
+inline const KernelSet* kernel_set(int M) {
+    switch (M) {
+        case 1: return kernel_set_M1();
+        case 2: return kernel_set_M2();
+        case 3: return kernel_set_M3();
+        case 4: return kernel_set_M4();
+        case 5: return kernel_set_M5();
+        case 6: return kernel_set_M6();
+        case 7: return kernel_set_M7();
+        case 8: return kernel_set_M8();
+        case 9: return kernel_set_M9();
+        case 10: return kernel_set_M10();
+        default: return nullptr;
+    }
+}
+
+// Generic kernels (util.hip).
+void launch_fill(double* p, long long n, double v, hipStream_t s);
+void launch_set_c64(double* p, long long idx, double re, double im, hipStream_t s);
+// out[g*nvals + o] (+)= sum_{b<G} part[(g*G + b)*stride + o], fixed order.
+void launch_reduce_partials(const double* part, int ngroups, int G, int stride, int nvals, double* out,
+                            int accumulate, hipStream_t s);
+// psi[i*nrhs + q] *= scale[q]
+void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s);
+
+}  // namespace fh

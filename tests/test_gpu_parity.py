@@ -1,0 +1,302 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Bars (set in the tests below):
+  * basis, ranks, occupations: bit-exact;
+  * H psi: relative 2-norm error <= 1e-13 (rounding of a sum of <= M^3 terms);
+  * amplitudes after RK4: ||psi_gpu - psi_cpu||_2 <= 1e-10;
+  * observables: relative error <= 1e-9.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle, derived, evolve, states
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import paper_2111_00050_amd as fh  # noqa: E402
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def _pair(M, sectors, omega, Lam, V):
+    return Oracle(M, M, omega, Lam, V, sectors), fh.Model(M, omega, Lam, V), fh.Basis(M, sectors)
+
+
+# ----------------------------------------------------------------- basis ---
+BASIS_CASES = [(1, 7), (2, 9), (3, 11), (4, 12), (5, 8), (5, 14), (6, 13), (7, 9), (8, 8), (9, 6), (10, 6)]
+
+
+@pytest.mark.parametrize("M,N", BASIS_CASES)
+def test_basis_bitexact(M, N):
+    sectors = [(N, p) for p in range(M)] + [(0, 0), (1, 1 % M)]
+    orc = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), sectors)
+    b = fh.Basis(M, sectors)
+    assert b.dims == orc.dims
+    assert b.offsets[:-1] == orc.offsets
+    occ = b.occupations().cpu().numpy()
+    want = orc.all_occupations()
+    assert np.array_equal(occ, want)
+    for s in range(len(sectors)):
+        o = torch.from_numpy(orc.occupations(s)).cuda()
+        idx = b.rank(s, o).cpu().numpy()
+        assert np.array_equal(idx, np.arange(orc.dims[s]))
+        back = b.unrank(s, torch.arange(orc.dims[s], dtype=torch.int64, device="cuda")).cpu().numpy()
+        assert np.array_equal(back, orc.occupations(s))
+    # vectors of another sector rank to -1
+    if M > 1:
+        o = torch.from_numpy(orc.occupations(0)).cuda()
+        assert np.all(b.rank(1, o).cpu().numpy() == -1)
+
+
+# ---------------------------------------------------------------- H psi ---
+def _model(kind, M, seed):
+    if kind == "contact":
+        return W.omega_quadratic(M), W.V_contact(M)
+    if kind == "longrange":
+        return W.omega_quadratic(M), W.V_longrange(M)
+    if kind == "sym":
+        return np.random.default_rng(seed).uniform(-1, 1, M), W.V_random_symmetric(M, seed)
+    return np.random.default_rng(seed).uniform(-1, 1, M), W.V_random(M, seed)
+
+
+HPSI_CASES = [
+    (1, [(n, 0) for n in range(0, 12)], "sym"),
+    (2, [(9, 0), (9, 1), (3, 1)], "nonsym"),
+    (3, [(12, p) for p in range(3)], "sym"),
+    (4, [(11, p) for p in range(4)] + [(2, 0)], "nonsym"),
+    (5, [(8, 2)], "contact"),
+    (5, [(12, p) for p in range(5)], "longrange"),
+    (6, [(10, p) for p in range(6)], "sym"),
+    (6, [(n, p) for n in range(0, 8) for p in range(6)], "contact"),
+    (7, [(8, 3), (7, 1)], "nonsym"),
+    (8, [(8, 0), (8, 5)], "longrange"),
+    (8, [(7, p) for p in range(8)], "sym"),
+    (9, [(6, 2), (6, 0)], "nonsym"),
+    (10, [(6, p) for p in range(10)], "contact"),
+    (10, [(5, 3), (6, 7)], "sym"),
+]
+
+
+@pytest.mark.parametrize("M,sectors,kind", HPSI_CASES, ids=[f"M{c[0]}-{c[2]}-{len(c[1])}sec" for c in HPSI_CASES])
+def test_apply_h_vs_oracle(M, sectors, kind):
+    omega, V = _model(kind, M, 100 + M)
+    orc, model, b = _pair(M, sectors, omega, 0.37, V)
+    x = W.random_psi(orc.total, 7)
+    want = orc.apply_h(x)
+    got = fh.apply_h(model, b, torch.from_numpy(x).cuda()).cpu().numpy()
+    assert _rel(got, want) <= 1e-13
+
+
+@pytest.mark.parametrize("nrhs", [2, 4, 8, 16])
+def test_apply_h_multi_rhs(nrhs):
+    M = 6
+    sectors = [(9, p) for p in range(M)]
+    omega, V = _model("longrange", M, 3)
+    orc, model, b = _pair(M, sectors, omega, 0.21, V)
+    X = W.random_psi(orc.total, 17, nrhs=nrhs)
+    got = fh.apply_h(model, b, torch.from_numpy(X).cuda()).cpu().numpy()
+    for q in range(nrhs):
+        single = fh.apply_h(model, b, torch.from_numpy(np.ascontiguousarray(X[:, q])).cuda()).cpu().numpy()
+        assert np.array_equal(got[:, q], single)
+        assert _rel(got[:, q], orc.apply_h(np.ascontiguousarray(X[:, q]))) <= 1e-13
+
+
+# -------------------------------------------------------------- moments ---
+@pytest.mark.parametrize("M,Nmax", [(1, 9), (2, 8), (3, 8), (5, 6), (6, 6), (8, 4), (10, 3)])
+def test_moments_vs_oracle(M, Nmax):
+    sectors = W.all_sectors(M, Nmax)
+    orc = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), sectors)
+    b = fh.Basis(M, sectors)
+    x = W.random_psi(orc.total, 5)
+    n2, a, Mm, A = fh.moments(b, torch.from_numpy(x).cuda())
+    wn2, wa, wM, wA = orc.moments(x)
+    scale = wn2
+    assert abs(n2 - wn2) <= 1e-12 * scale
+    assert np.abs(a - wa).max() <= 1e-12 * scale
+    assert np.abs(Mm - wM).max() <= 1e-12 * scale * Nmax
+    assert np.abs(A - wA).max() <= 1e-12 * scale * Nmax
+
+
+def test_moments_missing_partner_sectors():
+    """Terms whose image lies outside the retained sectors count as zero."""
+    M = 4
+    sectors = [(6, 1), (5, 0), (6, 3), (4, 2)]
+    orc = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), sectors)
+    b = fh.Basis(M, sectors)
+    x = W.random_psi(orc.total, 8)
+    got = fh.moments(b, torch.from_numpy(x).cuda())
+    want = orc.moments(x)
+    for g, w in zip(got, want):
+        assert np.allclose(g, w, rtol=0, atol=1e-12 * want[0])
+
+
+def test_derive_matches_oracle_on_gpu_moments():
+    M = 4
+    alpha = W.coherent_amplitudes(9, M, 2.5)
+    sectors = W.all_sectors(M, 16)
+    orc = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), sectors)
+    b = fh.Basis(M, sectors)
+    psi = fh.init_coherent(b, alpha)
+    got = fh.derive(M, *fh.moments(b, psi))
+    want = derived.observe(orc, states.coherent_state(orc, alpha))
+    for k in ("n_tot", "lambda_p", "vminus"):
+        assert abs(got[k] - want[k]) <= 1e-9 * max(1.0, abs(want[k]))
+    assert abs(got["Q"] - want["Q"]) <= 1e-9
+
+
+# ---------------------------------------------------------- initial states ---
+def test_initial_states_vs_oracle():
+    M = 5
+    sectors = W.all_sectors(M, 9)
+    orc = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), sectors)
+    b = fh.Basis(M, sectors)
+    al = np.stack([W.coherent_amplitudes(s, M, 2.0) for s in (1, 2)])
+    got = fh.init_coherent(b, al).cpu().numpy()
+    for q in range(2):
+        assert _rel(got[:, q], states.coherent_state(orc, al[q])) <= 1e-13
+    z = W.coherent_amplitudes(3, M, 4.0)
+    b6 = fh.Basis(M, [(6, p) for p in range(M)])
+    o6 = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), [(6, p) for p in range(M)])
+    assert _rel(fh.init_fieldnumber(b6, z).cpu().numpy(), states.fieldnumber_state(o6, z)) <= 1e-13
+    n = [2, 0, 1, 3, 0]
+    bn = fh.Basis(M, [(6, W.momentum(n, M))])
+    on = Oracle(M, M, np.zeros(M), 0.0, np.zeros((M,) * 4), [(6, W.momentum(n, M))])
+    assert np.array_equal(fh.init_number(bn, n).cpu().numpy(), states.number_state(on, n))
+
+
+# ------------------------------------------------------------------ RK4 ---
+def _oracle_run(orc, psi0, dt, nsteps, every):
+    return evolve.rk4(orc, psi0, dt, nsteps, every=every, observe=lambda s, t, p: orc.moments(p))
+
+
+def _check_records(M, res, recs, rhs=0):
+    """Relative 1e-9 on every observable.  Q = (n_tot - sum|<a>|^2)/n_tot and
+    V_- are differences of O(n_tot) terms, so each also gets an absolute floor
+    of 1e-12 (n_tot rounding, ~1e-16 n_tot, amplified by the cancellation)."""
+    assert len(res.records) == len(recs)
+    for r, (n2, a, Mm, A) in zip(res.records[:, rhs], recs):
+        g = fh.derive(M, *fh.unpack_moments(M, r))
+        o = derived.derive(n2, a, Mm, A)
+        for k in ("norm2", "n_tot", "lambda_p"):
+            assert abs(g[k] - o[k]) <= 1e-9 * max(abs(o[k]), 1e-300), k
+        floor = 1e-12 * max(1.0, o["n_tot"])
+        assert abs(g["Q"] - o["Q"]) <= 1e-9 * abs(o["Q"]) + floor
+        if np.isfinite(o["vminus"]):
+            assert abs(g["vminus"] - o["vminus"]) <= 1e-9 * abs(o["vminus"]) + floor
+
+
+def test_rk4_tiny_number_state_full_run():
+    w = W.tiny_number()
+    orc, model, b = _pair(w.M, w.sectors, w.omega, w.Lambda, w.V)
+    psi = fh.init_number(b, w.init_params)
+    res = fh.evolve_rk4(model, b, psi, w.dt, w.nsteps, every=w.every)
+    ref, recs = _oracle_run(orc, states.number_state(orc, w.init_params), w.dt, w.nsteps, w.every)
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-10
+    _check_records(w.M, res, recs)
+
+
+@pytest.mark.parametrize("flags", [0, fh.FH_PER_SECTOR, fh.FH_GRAPH, fh.FH_TIMING])
+def test_rk4_coherent_multisector(flags):
+    M, Lam = 4, 0.3
+    alpha = W.coherent_amplitudes(13, M, 2.0)
+    sectors = W.all_sectors(M, 12)
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    psi = fh.init_coherent(b, alpha)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        res = fh.evolve_rk4(model, b, psi, 2e-3, 150, every=50, flags=flags)
+    stream.synchronize()
+    ref, recs = _oracle_run(orc, states.coherent_state(orc, alpha), 2e-3, 150, 50)
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-10
+    _check_records(M, res, recs)
+    if flags & fh.FH_TIMING:
+        assert res.stage_launches == 4 * 150 and res.stage_ms > 0
+
+
+def test_batched_equals_per_sector_bitwise():
+    M = 5
+    alpha = W.coherent_amplitudes(2, M, 3.0)
+    sectors = W.all_sectors(M, 14)
+    model = fh.Model(M, W.omega_quadratic(M), 0.05, W.V_contact(M))
+    b = fh.Basis(M, sectors)
+    p1 = fh.init_coherent(b, alpha)
+    p2 = p1.clone()
+    fh.evolve_rk4(model, b, p1, 1e-3, 40)
+    fh.evolve_rk4(model, b, p2, 1e-3, 40, flags=fh.FH_PER_SECTOR)
+    assert torch.equal(p1, p2)
+
+
+def test_rk4_fieldnumber_multi_rhs():
+    M, N, nrhs = 5, 7, 4
+    n = np.array([3, 1, 0, 2, 1])
+    z = W.phase_draws(n, range(50, 50 + nrhs))
+    sectors = [(N, p) for p in range(M)]
+    omega, V = W.omega_linear(M), W.V_contact(M)
+    orc, model, b = _pair(M, sectors, omega, 0.1, V)
+    psi = fh.init_fieldnumber(b, z)
+    res = fh.evolve_rk4(model, b, psi, 5e-3, 60, every=30)
+    got = psi.cpu().numpy()
+    for q in range(nrhs):
+        ref, recs = _oracle_run(orc, states.fieldnumber_state(orc, z[q]), 5e-3, 60, 30)
+        assert np.linalg.norm(got[:, q] - ref) <= 1e-10
+        _check_records(M, res, recs, rhs=q)
+
+
+# ----------------------------------------------------- large sector, sampled ---
+def test_large_sector_sampled():
+    """The benchmark's sector (M=8, N=48, P=0): dimension, sampled ranks and
+    sampled rows of H psi against the oracle, in the benchmark's launch setup."""
+    w = W.large_sector()
+    orc = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    model = fh.Model(w.M, w.omega, w.Lambda, w.V)
+    b = fh.Basis(w.M, w.sectors)
+    assert b.total == orc.total == 25_366_335
+    rng = np.random.default_rng(4)
+    rows = np.sort(np.concatenate([rng.choice(b.total, 3000, replace=False), [0, 1, b.total - 1]]))
+    occ_all = orc.occupations(0)
+    occ = occ_all[rows]
+    got_occ = b.unrank(0, torch.from_numpy(rows).cuda()).cpu().numpy()
+    assert np.array_equal(got_occ, occ)
+    assert np.array_equal(b.rank(0, torch.from_numpy(np.ascontiguousarray(occ)).cuda()).cpu().numpy(), rows)
+    x = W.random_psi(b.total, 21)
+    got = fh.apply_h(model, b, torch.from_numpy(x).cuda()).cpu().numpy()[rows]
+    want = orc.apply_h_rows(x, rows)
+    assert _rel(got, want) <= 1e-13
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+# -------------------------------------------------------------- adjoint ---
+def test_adjoint_vs_oracle():
+    M, Lam, dt, nsteps = 3, 0.35, 5e-3, 30
+    sectors = W.all_sectors(M, 9)
+    omega = W.omega_quadratic(M)
+    V = W.V_longrange(M) + 0.3 * W.V_contact(M)
+    alpha = W.coherent_amplitudes(31, M, 1.5)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    psi0o = states.coherent_state(orc, alpha)
+    for obj, mk in ((fh.FH_J_Q, evolve.objective_Q), (fh.FH_J_PO, evolve.objective_PO),
+                    (fh.FH_J_NMODE, lambda o: evolve.objective_mode_occupation(o, 1))):
+        ref = evolve.adjoint(orc, psi0o, dt, nsteps, mk(orc))
+        psi0 = fh.init_coherent(b, alpha)
+        res = fh.adjoint_rk4(model, b, psi0, dt, nsteps, 7, obj, mode=1)
+        assert abs(res["J"][0] - ref["J"]) <= 1e-10
+        assert abs(res["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
+        # only momentum-conserving entries are parameters of the model; the
+        # others are reported as exactly zero
+        cons = W.V_contact(M) != 0
+        assert np.abs(res["dV"][0][cons] - ref["dV"][cons]).max() <= 1e-9 * max(1, np.abs(ref["dV"]).max())
+        assert np.all(res["dV"][0][~cons] == 0)
+        lam0 = res["lambda0"].cpu().numpy()
+        assert _rel(lam0, ref["g0"]) <= 1e-10
+        dre, dim = fh.coherent_vjp(b, alpha, res["lambda0"])
+        wre, wim = evolve.coherent_alpha_gradient(orc, alpha, psi0o, ref["g0"])
+        assert np.abs(dre[0] - wre).max() <= 1e-9 * max(1, np.abs(wre).max())
+        assert np.abs(dim[0] - wim).max() <= 1e-9 * max(1, np.abs(wim).max())
