@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--xcd-order", type=int, default=1)
+    ap.add_argument("--tile-order", type=int, default=0)
+    ap.add_argument("--prefix-modes", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (got --gpus {args.gpus}); "
@@ -112,6 +114,7 @@ def main():
     model = fh.Model(w.M, w.omega, w.Lambda, w.V)
     basis = fh.Basis(w.M, w.sectors)
     basis.set_launch(args.blocks_per_cu, args.xcd_order)
+    basis.set_tile_order(args.tile_order, args.prefix_modes)
     D = basis.total
     psi = fh.init_number(basis, w.init_params)
     work = torch.empty(3 * D, dtype=torch.complex128, device="cuda")

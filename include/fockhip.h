@@ -83,8 +83,8 @@ fh_status fh_model_destroy(fh_model* m);
  * Sector list (N[s], P[s]), s < nsec, host arrays; duplicates are EINVAL.
  * Empty sectors (dimension 0) are allowed.  Builds the counting tables of the
  * lexicographic rank (Sec. III.B; sizes as in App. A) on the host with
- * overflow checks (FH_EOVERFLOW if a sector exceeds 2^31-1 states) and
- * uploads them. */
+ * overflow checks (FH_EOVERFLOW if a sector has 2^28 or more states: gathers
+ * inside a sector use 32-bit byte offsets) and uploads them. */
 fh_status fh_basis_create(int M, int pmod, int nsec, const int32_t* N, const int32_t* P,
                           fh_basis** out);
 fh_status fh_basis_destroy(fh_basis* b);
@@ -179,6 +179,15 @@ fh_status fh_evolve_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* 
  * order (0 = plain round robin, 1 = contiguous tile ranges per XCD).
  * Not thread-safe with concurrent calls on the same basis. */
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
+/* Tiling and schedule of each sector's rows; storage stays lexicographic and
+ * results do not depend on it.  Tiles (<= 256 consecutive rows) never cross a
+ * change of the occupations of the first prefix_modes modes (0 = plain 256-row
+ * chunks; at most min(M-1, 8)).  order 0 visits the tiles lexicographically;
+ * order 1 visits the blocks of equal prefix along a Morton (bit-interleaved)
+ * curve over the prefix, so that concurrently processed tiles and the blocks
+ * their neighbours live in (prefix changes of at most +-2 per mode) stay in
+ * cache together.  Not thread-safe with concurrent calls on the same basis. */
+fh_status fh_basis_set_tile_order(fh_basis* b, int order, int prefix_modes);
 
 /* ---------------------------------------------------------------- adjoint --
  * Discrete adjoint of nsteps RK4 steps from psi0 (device), for the objective

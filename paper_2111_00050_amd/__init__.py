@@ -62,6 +62,7 @@ SIGNATURES = {
     "fh_basis_unrank": (_I, [_P, _I, _I64, _P, _P, _P]),
     "fh_basis_occupations": (_I, [_P, _P, _P]),
     "fh_basis_set_launch": (_I, [_P, _I, _I]),
+    "fh_basis_set_tile_order": (_I, [_P, _I, _I]),
     "fh_init_number": (_I, [_P, _P, _I, _P, _P]),
     "fh_init_coherent": (_I, [_P, _P, _I, _P, _P]),
     "fh_init_fieldnumber": (_I, [_P, _P, _I, _P, _P]),
@@ -179,6 +180,11 @@ class Basis:
 
     def set_launch(self, blocks_per_cu=0, xcd_order=1):
         _check(_lib.fh_basis_set_launch(self._h, int(blocks_per_cu), int(xcd_order)))
+
+    def set_tile_order(self, order=1, prefix_modes=3):
+        """Tiles split at changes of the first prefix_modes occupations, visited
+        lexicographically (order 0) or along a Morton curve over the prefix (1)."""
+        _check(_lib.fh_basis_set_tile_order(self._h, int(order), int(prefix_modes)))
 
     def rank(self, sec, occ):
         torch = _torch()

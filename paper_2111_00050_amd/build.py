@@ -1,10 +1,12 @@
 """Build libfockhip.so in-tree with hipcc for gfx950.
 
-    python -m paper_2111_00050_amd.build            # compile every unit, link
-    python -m paper_2111_00050_amd.build --jobs 8
+    python paper_2111_00050_amd/build.py             # compile every unit, link
+    python paper_2111_00050_amd/build.py --incremental
 
-Each mode count M = 1..10 has its own translation unit (inst.hip with
--DFH_INST_M=M) so that the large, fully unrolled kernels compile in parallel.
+The fully unrolled stage kernel is instantiated once per (M, nrhs) in its
+own translation unit (inst_stage.hip), the remaining kernels once per M
+(inst_aux.hip), so that the large units compile in parallel.
+build(incremental=True) recompiles only units older than the sources.
 """
 from __future__ import annotations
 
@@ -22,6 +24,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfockhip.so")
 ARCH = os.environ.get("FH_OFFLOAD_ARCH", "gfx950")
 MODES = list(range(1, 11))
+NRHS = (1, 2, 4, 8, 16)
 
 COMMON = [
     "-O3",
@@ -42,14 +45,28 @@ def hipcc() -> str:
 
 
 def _units():
+    """(source, object, extra flags, cost estimate) for every unit."""
     units = []
     for m in MODES:
-        units.append((os.path.join(CSRC, "inst.hip"), os.path.join(OBJ, f"inst_M{m}.o"), [f"-DFH_INST_M={m}"]))
+        for r in NRHS:
+            units.append((os.path.join(CSRC, "inst_stage.hip"), os.path.join(OBJ, f"stage_M{m}_R{r}.o"),
+                          [f"-DFH_INST_M={m}", f"-DFH_INST_R={r}"], m ** 3 * (1 + r / 4)))
+        units.append((os.path.join(CSRC, "inst_aux.hip"), os.path.join(OBJ, f"aux_M{m}.o"),
+                      [f"-DFH_INST_M={m}"], m ** 3))
     for f in ("util.hip", "api.hip", "derive.cpp"):
         src = os.path.join(CSRC, f)
         extra = ["-x", "hip"] if f.endswith(".cpp") else []
-        units.append((src, os.path.join(OBJ, os.path.splitext(f)[0] + ".o"), extra))
+        units.append((src, os.path.join(OBJ, os.path.splitext(f)[0] + ".o"), extra, 1))
     return units
+
+
+def _stale(src, obj):
+    if not os.path.exists(obj):
+        return True
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".hpp")]
+    deps.append(os.path.join(HERE, "..", "include", "fockhip.h"))
+    t = os.path.getmtime(obj)
+    return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
 
 
 def _compile(cc, src, obj, extra):
@@ -62,16 +79,16 @@ def _compile(cc, src, obj, extra):
     return obj, time.time() - t0, msgs
 
 
-def build(jobs: int | None = None, verbose: bool = True) -> str:
+def build(jobs: int | None = None, verbose: bool = True, incremental: bool = False) -> str:
     cc = hipcc()
     os.makedirs(OBJ, exist_ok=True)
     jobs = jobs or max(1, min(8, os.cpu_count() or 1))
     units = _units()
-    # longest units (large M) first
-    units.sort(key=lambda u: -int(u[2][0].split("=")[1]) if u[2] and u[2][0].startswith("-DFH_INST_M") else 0)
+    todo = [u for u in units if not incremental or _stale(u[0], u[1])]
+    todo.sort(key=lambda u: -u[3])  # longest first
     t0 = time.time()
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        futs = [ex.submit(_compile, cc, *u) for u in units]
+        futs = [ex.submit(_compile, cc, *u[:3]) for u in todo]
         for f in cf.as_completed(futs):
             obj, dt, msgs = f.result()
             if verbose:
@@ -92,6 +109,7 @@ def build(jobs: int | None = None, verbose: bool = True) -> str:
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
-    build(a.jobs)
+    build(a.jobs, incremental=a.incremental)
     sys.exit(0)

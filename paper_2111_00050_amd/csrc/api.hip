@@ -270,9 +270,10 @@ fh_status make_basis(int M, int pmod, int nsec, const int32_t* N, const int32_t*
     int64_t off = 0;
     for (int s = 0; s < nsec; ++s) {
         const int64_t d = b->D_at(0, N[s], P[s]);
-        if (d > INT32_MAX) {
+        if (d >= ((int64_t)1 << 28)) {
+            // Single-rhs gathers use 32-bit byte offsets inside a sector.
             delete b;
-            set_error("fh_basis_create: a sector has more than 2^31-1 states");
+            set_error("fh_basis_create: a sector has 2^28 or more states (limit of this build)");
             return FH_EOVERFLOW;
         }
         b->dim[s] = d;
@@ -347,6 +348,25 @@ int64_t host_rank(const fh_basis* b, int sec, const uint8_t* occ) {
         Q = posmod((long long)Q - (long long)m * occ[m], p);
     }
     return r;
+}
+
+// Inverse of host_rank: the occupation vector at rank r of sector sec.
+void host_unrank(const fh_basis* b, int sec, int64_t r, int* occ) {
+    const int M = b->M, p = b->pmod;
+    int R = b->N[sec], Q = b->P[sec];
+    for (int m = 0; m < M - 1; ++m) {
+        int v = 0;
+        while (v < R) {
+            const int64_t cnt = b->D_at(m + 1, R - v, posmod((long long)Q - (long long)m * v, p));
+            if (r < cnt) break;
+            r -= cnt;
+            ++v;
+        }
+        occ[m] = v;
+        R -= v;
+        Q = posmod((long long)Q - (long long)m * v, p);
+    }
+    occ[M - 1] = R;
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
@@ -441,14 +461,14 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
             if (nt == 0) continue;
             a.tiles = b->d_tiles + b->tile_begin[sec];
             a.ntiles = nt;
-            b->ks->stage(slot, a, persistent_grid(b, fn, lds, nt), lds, s);
+            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt), lds, s);
         }
     } else {
         const int nt = (int)b->tiles.size();
         if (nt > 0) {
             a.tiles = b->d_tiles;
             a.ntiles = nt;
-            b->ks->stage(slot, a, persistent_grid(b, fn, lds, nt), lds, s);
+            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt), lds, s);
         }
     }
     FH_HIP(hipGetLastError());
@@ -608,6 +628,66 @@ fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order) {
     b->blocks_per_cu = blocks_per_cu;
     b->xcd_order = xcd_order;
     return FH_OK;
+}
+
+fh_status fh_basis_set_tile_order(fh_basis* b, int order, int prefix_modes) {
+    return Guard::run([&]() -> fh_status {
+        FH_REQUIRE(b != nullptr, FH_EINVAL, "fh_basis_set_tile_order: basis is NULL");
+        FH_REQUIRE(order == 0 || order == 1, FH_EINVAL, "fh_basis_set_tile_order: order must be 0 or 1");
+        FH_REQUIRE(prefix_modes >= 0 && prefix_modes <= std::min(b->M - 1, 8), FH_EINVAL,
+                   "fh_basis_set_tile_order: prefix_modes must be in [0, min(M-1, 8)]");
+        const int M = b->M, p = b->pmod, h = prefix_modes;
+        std::vector<Tile> tiles;
+        std::vector<int> begin(b->nsec + 1);
+        for (int s = 0; s < b->nsec; ++s) {
+            begin[s] = (int)tiles.size();
+            // Blocks: rows sharing the occupations of modes 0..h-1 are
+            // contiguous in lexicographic order; walk the prefixes in that
+            // order, with block sizes D_h(remaining bosons, remaining momentum).
+            std::vector<std::pair<uint64_t, Tile>> keyed;
+            std::vector<int> pre(std::max(h, 1), 0);
+            int64_t start = 0;
+            auto emit = [&](int64_t size) {
+                uint64_t key = 0;  // Morton key: interleave the bits of the prefix
+                for (int bit = 7; bit >= 0; --bit)
+                    for (int m = 0; m < h; ++m) key = (key << 1) | (uint64_t)((pre[m] >> bit) & 1);
+                for (int64_t r = 0; r < size; r += kTileRows)
+                    keyed.push_back({key, Tile{s, (int)(start + r), (int)std::min<int64_t>(kTileRows, size - r), 0}});
+                start += size;
+            };
+            auto rec = [&](auto&& self, int m, int R, int Q) -> void {
+                if (m == h) {
+                    const int64_t size = b->D_at(h, R, Q);
+                    if (size > 0) emit(size);
+                    return;
+                }
+                for (int v = 0; v <= R; ++v) {
+                    pre[m] = v;
+                    self(self, m + 1, R - v, posmod((long long)Q - (long long)m * v, p));
+                }
+            };
+            rec(rec, 0, b->N[s], b->P[s]);
+            FH_REQUIRE(start == b->dim[s], FH_EINVAL, "fh_basis_set_tile_order: internal block count mismatch");
+            if (order == 1)
+                std::stable_sort(keyed.begin(), keyed.end(),
+                                 [](const auto& x, const auto& y) { return x.first < y.first; });
+            for (auto& kt : keyed) tiles.push_back(kt.second);
+        }
+        begin[b->nsec] = (int)tiles.size();
+        if (tiles.size() > b->tiles.size() || b->d_tiles == nullptr) {
+            Tile* d = nullptr;
+            FH_HIP(hipMalloc(&d, sizeof(Tile) * std::max<size_t>(1, tiles.size())));
+            FH_HIP(hipDeviceSynchronize());
+            (void)hipFree(b->d_tiles);
+            b->d_tiles = d;
+        }
+        b->tiles.swap(tiles);
+        b->tile_begin.swap(begin);
+        (void)M;
+        if (!b->tiles.empty())
+            FH_HIP(hipMemcpy(b->d_tiles, b->tiles.data(), sizeof(Tile) * b->tiles.size(), hipMemcpyHostToDevice));
+        return FH_OK;
+    });
 }
 
 fh_status fh_basis_rank(const fh_basis* b, int sec, int64_t count, const uint8_t* occ, int64_t* idx, void* stream) {

@@ -30,6 +30,13 @@ namespace fh {
 constexpr int kMaxM = 10;
 constexpr int kTileRows = 256;  // one row per thread, four wave64s per workgroup
 constexpr int kRBias = 2;       // rank table rows R = -2 .. Nmax+2
+constexpr int kGatherBatch = 16;  // neighbour gathers issued together per thread
+#ifndef FH_STAGE_BLOCKS_PER_CU
+#define FH_STAGE_BLOCKS_PER_CU 1
+#endif
+// Occupancy target of the stage kernel (workgroups of 256 per CU); it caps the
+// registers per thread at 512 / (4 * blocks) per SIMD lane.
+constexpr int kStageBlocksPerCU = FH_STAGE_BLOCKS_PER_CU;
 
 template <int M>
 struct PairTable {

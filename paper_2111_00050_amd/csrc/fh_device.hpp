@@ -138,6 +138,15 @@ __device__ __forceinline__ int move_rank(const int* sT, const int (&key)[M], con
     return r;
 }
 
+typedef double v2d __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ v2d nt_load(const double* p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
+}
+__device__ __forceinline__ void nt_store(double* p, v2d v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<v2d*>(p));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -172,7 +181,7 @@ __device__ __forceinline__ void stage_tables(const int* T, int Tn, const double*
 
 // ------------------------------------------------------------ H psi stage --
 template <int M, int NRHS>
-__global__ __launch_bounds__(kTileRows) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(StageArgs A) {
     using CB = Combos<M>;
     constexpr int NP = CB::NP;
     extern __shared__ int smem[];
@@ -181,7 +190,7 @@ __global__ __launch_bounds__(kTileRows) void stage_kernel(StageArgs A) {
     stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
 
     const double* __restrict__ cf = A.coef;
-    const double2* __restrict__ X = reinterpret_cast<const double2*>(A.x);
+    const double2* X = reinterpret_cast<const double2*>(A.x);
     const int vb = virtual_block(A.xcd_order);
     for (int t = vb; t < A.ntiles; t += gridDim.x) {
         const Tile tl = A.tiles[t];
@@ -210,75 +219,147 @@ __global__ __launch_bounds__(kTileRows) void stage_kernel(StageArgs A) {
         });
 
         const long long soff = sc.off;
-        const double2* __restrict__ xs = X + soff * NRHS;
+        const double2* xs = X + soff * NRHS;
         double2 acc[NRHS];
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) acc[q] = make_double2(0.0, 0.0);
 
-        static_for<0, NP>([&](auto P1) {
-            constexpr int p1 = decltype(P1)::value;
-            constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
-            if constexpr (CB::class_size(CB::cls(p1)) > 1) {
-                const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
-                if (valid) {
-                    const double cij = (i == j) ? sq[i] * sSq[n[i] - 1] : sq[i] * sq[j];
-                    double2 pacc[NRHS];
-#pragma unroll
-                    for (int q = 0; q < NRHS; ++q) pacc[q] = make_double2(0.0, 0.0);
-                    static_for<0, NP>([&](auto P2) {
-                        constexpr int p2 = decltype(P2)::value;
-                        if constexpr (CB::linked(p1, p2)) {
+        if constexpr (NRHS == 1) {
+            // One momentum class at a time, in chunks of up to kGatherBatch
+            // combinations: all neighbour ranks first, then every gather of the
+            // chunk in flight together, then the FMAs.  Lanes whose row pair
+            // cannot be annihilated (c_ij == 0) gather their own row with a
+            // zero weight, so the chunk is straight-line code.
+            const char* xb = reinterpret_cast<const char*>(xs);
+            static_for<0, M>([&](auto Cc) {
+                constexpr int c = decltype(Cc)::value;
+                constexpr int S = CB::class_size(c);
+                if constexpr (S > 1) {
+                    constexpr int NQ = S * (S - 1);
+                    double cij[S];
+                    static_for<0, S>([&](auto R1) {
+                        constexpr int r1 = decltype(R1)::value;
+                        constexpr int p1 = CB::class_member(c, r1);
+                        constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+                        // sqrt(n_i (n_j - d_ij)); zero exactly when the pair is empty
+                        if constexpr (i == j) cij[r1] = sq[i] * sSq[n[i] > 0 ? n[i] - 1 : 0];
+                        else cij[r1] = sq[i] * sq[j];
+                    });
+                    constexpr int QB = kGatherBatch;
+                    constexpr int NCH = (NQ + QB - 1) / QB;
+                    static_for<0, NCH>([&](auto Ch) {
+                        constexpr int q0 = decltype(Ch)::value * QB;
+                        constexpr int NQC = (NQ - q0) < QB ? (NQ - q0) : QB;
+                        unsigned off[NQC];
+                        static_for<0, NQC>([&](auto Q) {
+                            constexpr int q = q0 + decltype(Q)::value;
+                            constexpr int r1 = q / (S - 1), t = q % (S - 1), r2 = t < r1 ? t : t + 1;
+                            constexpr int p1 = CB::class_member(c, r1), p2 = CB::class_member(c, r2);
+                            constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
                             constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
-                            constexpr int c = CB::index(p1, p2);
                             constexpr int lo = i < k ? i : k;
                             constexpr int hi = j > l ? j : l;
                             int r = row + (C[hi] - C[lo]);
-                            static_for<lo + 1, hi + 1>([&](auto S) {
-                                constexpr int s = decltype(S)::value;
+                            static_for<lo + 1, hi + 1>([&](auto Sx) {
+                                constexpr int s = decltype(Sx)::value;
                                 r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
                             });
+                            off[decltype(Q)::value] = (unsigned)(cij[r1] != 0.0 ? r : row) * 16u;
+                        });
+                        double2 v[NQC];
+                        static_for<0, NQC>([&](auto Q) {
+                            v[decltype(Q)::value] = *reinterpret_cast<const double2*>(xb + off[decltype(Q)::value]);
+                        });
+                        static_for<0, NQC>([&](auto Q) {
+                            constexpr int q = q0 + decltype(Q)::value;
+                            constexpr int r1 = q / (S - 1), t = q % (S - 1), r2 = t < r1 ? t : t + 1;
+                            constexpr int p1 = CB::class_member(c, r1), p2 = CB::class_member(c, r2);
+                            constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
+                            constexpr int ci = M + NP + CB::index(p1, p2);
                             const double ckl = (k == l) ? sqp[k] * sSq[n[k] + 2] : sqp[k] * sqp[l];
-                            const double w = cf[M + NP + c] * ckl;
-                            const double2* src = xs + (long long)r * NRHS;
-#pragma unroll
-                            for (int q = 0; q < NRHS; ++q) {
-                                const double2 v = src[q];
-                                pacc[q].x = fma(w, v.x, pacc[q].x);
-                                pacc[q].y = fma(w, v.y, pacc[q].y);
-                            }
-                        }
+                            const double w = cf[ci] * (cij[r1] * ckl);
+                            acc[0].x = fma(w, v[decltype(Q)::value].x, acc[0].x);
+                            acc[0].y = fma(w, v[decltype(Q)::value].y, acc[0].y);
+                        });
+                        // Keep chunks apart: no table read is reused across them
+                        // and the scheduler does not interleave their gathers,
+                        // which would otherwise hoist everything and spill.
+                        asm volatile("" ::: "memory");
+                        __builtin_amdgcn_sched_barrier(0);
                     });
+                }
+            });
+        } else {
+            // Several right-hand sides: each neighbour is one contiguous run
+            // of NRHS amplitudes, already NRHS loads in flight per gather.
+            static_for<0, NP>([&](auto P1) {
+                constexpr int p1 = decltype(P1)::value;
+                constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+                if constexpr (CB::class_size(CB::cls(p1)) > 1) {
+                    const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
+                    if (valid) {
+                        const double cij = (i == j) ? sq[i] * sSq[n[i] - 1] : sq[i] * sq[j];
+                        double2 pacc[NRHS];
 #pragma unroll
-                    for (int q = 0; q < NRHS; ++q) {
-                        acc[q].x = fma(cij, pacc[q].x, acc[q].x);
-                        acc[q].y = fma(cij, pacc[q].y, acc[q].y);
+                        for (int q = 0; q < NRHS; ++q) pacc[q] = make_double2(0.0, 0.0);
+                        static_for<0, NP>([&](auto P2) {
+                            constexpr int p2 = decltype(P2)::value;
+                            if constexpr (CB::linked(p1, p2)) {
+                                constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
+                                constexpr int ci = M + NP + CB::index(p1, p2);
+                                constexpr int lo = i < k ? i : k;
+                                constexpr int hi = j > l ? j : l;
+                                int r = row + (C[hi] - C[lo]);
+                                static_for<lo + 1, hi + 1>([&](auto Sx) {
+                                    constexpr int s = decltype(Sx)::value;
+                                    r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
+                                });
+                                const double ckl = (k == l) ? sqp[k] * sSq[n[k] + 2] : sqp[k] * sqp[l];
+                                const double w = cf[ci] * ckl;
+                                const double2* src = xs + (long long)r * NRHS;
+#pragma unroll
+                                for (int q = 0; q < NRHS; ++q) {
+                                    const double2 v = src[q];
+                                    pacc[q].x = fma(w, v.x, pacc[q].x);
+                                    pacc[q].y = fma(w, v.y, pacc[q].y);
+                                }
+                            }
+                        });
+#pragma unroll
+                        for (int q = 0; q < NRHS; ++q) {
+                            acc[q].x = fma(cij, pacc[q].x, acc[q].x);
+                            acc[q].y = fma(cij, pacc[q].y, acc[q].y);
+                        }
                     }
                 }
-            }
-        });
+            });
+        }
 
         const long long e = (soff + row) * NRHS;
 #pragma unroll
         for (int q = 0; q < NRHS; ++q) {
             const double2 xv = X[e + q];
-            double2 h;
-            h.x = fma(diag, xv.x, acc[q].x);
-            h.y = fma(diag, xv.y, acc[q].y);
+            double2 h1;
+            h1.x = fma(diag, xv.x, acc[q].x);
+            h1.y = fma(diag, xv.y, acc[q].y);
             if (A.mode == kApply) {
-                reinterpret_cast<double2*>(A.out)[e + q] = h;
+                reinterpret_cast<double2*>(A.out)[e + q] = h1;
                 continue;
             }
             double2 kk;
-            kk.x = A.ks_re * h.x - A.ks_im * h.y;
-            kk.y = A.ks_re * h.y + A.ks_im * h.x;
+            kk.x = A.ks_re * h1.x - A.ks_im * h1.y;
+            kk.y = A.ks_re * h1.y + A.ks_im * h1.x;
+            // base, acc and baseout are touched once per row per stage: stream
+            // them past the caches (non-temporal) so that the gathered vector
+            // keeps L2 and the memory-side cache.
             if (A.mode == kLast) {
-                const double2 ac = reinterpret_cast<const double2*>(A.acc)[e + q];
-                reinterpret_cast<double2*>(A.baseout)[e + q] = make_double2(fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y));
+                const v2d ac = nt_load(A.acc + 2 * (e + q));
+                nt_store(A.baseout + 2 * (e + q), v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
                 continue;
             }
-            const double2 bs = reinterpret_cast<const double2*>(A.base)[e + q];
-            const double2 ac = (A.mode == kFirst) ? bs : reinterpret_cast<const double2*>(A.acc)[e + q];
-            reinterpret_cast<double2*>(A.acc)[e + q] = make_double2(fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y));
+            const v2d bs = nt_load(A.base + 2 * (e + q));
+            const v2d ac = (A.mode == kFirst) ? bs : nt_load(A.acc + 2 * (e + q));
+            nt_store(A.acc + 2 * (e + q), v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
             reinterpret_cast<double2*>(A.ynext)[e + q] =
                 make_double2(fma(A.b, kk.x, A.c0 * bs.x), fma(A.b, kk.y, A.c0 * bs.y));
         }

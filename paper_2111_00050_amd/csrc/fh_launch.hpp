@@ -19,10 +19,16 @@ inline int nrhs_slot(int nrhs) {
     }
 }
 
+using StageLaunch = void (*)(const StageArgs&, int grid, size_t lds, hipStream_t);
+struct StageEntry {
+    const void* fn;
+    StageLaunch launch;
+};
+
 struct KernelSet {
     int M;
     const void* stage_fn[kNrhsVariants];
-    void (*stage)(int slot, const StageArgs&, int grid, size_t lds, hipStream_t);
+    StageLaunch stage[kNrhsVariants];
     const void* moments_fn;
     void (*moments)(const MomArgs&, int grid, int groups, size_t lds, hipStream_t);
     const void* onebody_fn;

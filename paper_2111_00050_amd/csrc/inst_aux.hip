@@ -1,5 +1,7 @@
-// inst.hip -- instantiates every kernel of fh_device.hpp for one mode count.
-// Compiled once per M with -DFH_INST_M=<M>.
+// inst_aux.hip -- instantiates every kernel of fh_device.hpp except the
+// stage kernel (inst_stage.hip) for one mode count, and assembles the kernel
+// set of that M.  Compiled once per M with -DFH_INST_M=<M>.
+// The stage kernel template is only declared here, never instantiated.
 #include "fh_device.hpp"
 #include "fh_launch.hpp"
 
@@ -13,22 +15,6 @@
 namespace fh {
 namespace {
 constexpr int kM = FH_INST_M;
-
-template <int NR>
-void stage_nr(const StageArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<kM, NR>), dim3(grid), dim3(kTileRows), lds, s, a);
-}
-
-void stage_any(int slot, const StageArgs& a, int grid, size_t lds, hipStream_t s) {
-    switch (slot) {
-        case 0: stage_nr<1>(a, grid, lds, s); break;
-        case 1: stage_nr<2>(a, grid, lds, s); break;
-        case 2: stage_nr<4>(a, grid, lds, s); break;
-        case 3: stage_nr<8>(a, grid, lds, s); break;
-        case 4: stage_nr<16>(a, grid, lds, s); break;
-        default: break;
-    }
-}
 
 void moments_l(const MomArgs& a, int grid, int groups, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((moments_kernel<kM>), dim3(grid, groups), dim3(kTileRows), lds, s, a);
@@ -55,13 +41,19 @@ void unrank_l(const RankArgs& a, hipStream_t s) {
 }
 }  // namespace
 
+#define FH_STAGE(r) FH_CAT(FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R), r)()
+StageEntry FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R1)();
+StageEntry FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R2)();
+StageEntry FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R4)();
+StageEntry FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R8)();
+StageEntry FH_CAT(FH_CAT(stage_entry_M, FH_INST_M), _R16)();
+
 const KernelSet* FH_CAT(kernel_set_M, FH_INST_M)() {
+    static const StageEntry st[kNrhsVariants] = {FH_STAGE(1), FH_STAGE(2), FH_STAGE(4), FH_STAGE(8), FH_STAGE(16)};
     static const KernelSet ks = {
         kM,
-        {reinterpret_cast<const void*>(&stage_kernel<kM, 1>), reinterpret_cast<const void*>(&stage_kernel<kM, 2>),
-         reinterpret_cast<const void*>(&stage_kernel<kM, 4>), reinterpret_cast<const void*>(&stage_kernel<kM, 8>),
-         reinterpret_cast<const void*>(&stage_kernel<kM, 16>)},
-        &stage_any,
+        {st[0].fn, st[1].fn, st[2].fn, st[3].fn, st[4].fn},
+        {st[0].launch, st[1].launch, st[2].launch, st[3].launch, st[4].launch},
         reinterpret_cast<const void*>(&moments_kernel<kM>),
         &moments_l,
         reinterpret_cast<const void*>(&onebody_kernel<kM>),
