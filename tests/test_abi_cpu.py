@@ -1,0 +1,90 @@
+"""C ABI checks that need no GPU: the library loads, exports every function
+declared in include/fockhip.h with the binding's signature, and the host-only
+entry points (argument validation, fh_derive) behave as documented."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fockhip.h")
+LIB = os.path.join(ROOT, "paper_2111_00050_amd", "libfockhip.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libfockhip.so not built")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fh_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = ctypes.CDLL(LIB)
+    names = header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), f"{n} declared in fockhip.h but not exported"
+
+
+def test_binding_covers_the_header():
+    import paper_2111_00050_amd as fh
+
+    assert set(header_functions()) == set(fh.SIGNATURES)
+
+
+def test_host_validation_paths():
+    import paper_2111_00050_amd as fh
+
+    lib = fh._lib
+    h = ctypes.c_void_p()
+    M = 3
+    om = np.zeros(M)
+    V = np.zeros((M,) * 4)
+    # M out of range / pmod != M are rejected before any device work
+    assert lib.fh_model_create(11, 11, fh._np_ptr(np.zeros(11)), 1.0, fh._np_ptr(np.zeros((11,) * 4)),
+                               ctypes.byref(h)) == fh.FH_EUNSUPPORTED
+    assert lib.fh_model_create(M, M + 1, fh._np_ptr(om), 1.0, fh._np_ptr(V), ctypes.byref(h)) == fh.FH_EUNSUPPORTED
+    # a non-conserving interaction entry: 0 + 0 != 0 + 1 (mod 3)
+    Vb = V.copy()
+    Vb[0, 0, 0, 1] = 1.0
+    assert lib.fh_model_create(M, M, fh._np_ptr(om), 1.0, fh._np_ptr(Vb), ctypes.byref(h)) == fh.FH_EINVAL
+    assert b"conserve" in lib.fh_last_error()
+    Vn = V.copy()
+    Vn[0, 0, 0, 0] = np.nan
+    assert lib.fh_model_create(M, M, fh._np_ptr(om), 1.0, fh._np_ptr(Vn), ctypes.byref(h)) == fh.FH_EINVAL
+    # duplicate sectors, bad P, no sectors
+    N = np.array([4, 4], np.int32)
+    P = np.array([1, 1], np.int32)
+    assert lib.fh_basis_create(M, M, 2, fh._np_ptr(N), fh._np_ptr(P), ctypes.byref(h)) == fh.FH_EINVAL
+    P2 = np.array([0, 3], np.int32)
+    assert lib.fh_basis_create(M, M, 2, fh._np_ptr(N), fh._np_ptr(P2), ctypes.byref(h)) == fh.FH_EINVAL
+    assert lib.fh_basis_create(M, M, 0, fh._np_ptr(N), fh._np_ptr(P), ctypes.byref(h)) == fh.FH_EINVAL
+    assert lib.fh_adjoint_work_states(0, 10) == -1
+    assert lib.fh_adjoint_work_states(3000, 100) == 30 + 100 + 10
+
+
+def test_derive_host_only_against_oracle():
+    """fh_derive (own Jacobi eigensolver) against the oracle's numpy path on
+    moments of random states: Hermitian M, random <a>, symmetric A."""
+    import paper_2111_00050_amd as fh
+    from oracle import derived
+
+    rng = np.random.default_rng(3)
+    for M in (1, 2, 5, 10):
+        X = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+        Mij = X.conj().T @ X + M * np.eye(M)
+        a = 0.3 * (rng.standard_normal(M) + 1j * rng.standard_normal(M))
+        A = rng.standard_normal((M, M)) + 1j * rng.standard_normal((M, M))
+        A = A + A.T
+        n2 = 1.7
+        g = fh.derive(M, n2, a * n2, Mij * n2, A * n2)
+        o = derived.derive(n2, a * n2, Mij * n2, A * n2)
+        for k in ("n_tot", "Q", "lambda_p", "po_deficit", "vminus"):
+            assert abs(g[k] - o[k]) <= 1e-12 * max(1.0, abs(o[k])), (M, k)
+        np.testing.assert_allclose(g["vminus_mode"], o["vminus_mode"], rtol=1e-12, atol=1e-12)
+        # eigenvector up to a phase
+        ph = np.vdot(o["xi"], g["xi"])
+        assert abs(abs(ph) - 1) < 1e-10
