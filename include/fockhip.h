@@ -188,6 +188,17 @@ fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
  * their neighbours live in (prefix changes of at most +-2 per mode) stay in
  * cache together.  Not thread-safe with concurrent calls on the same basis. */
 fh_status fh_basis_set_tile_order(fh_basis* b, int order, int prefix_modes);
+/* Autotuner: times one H psi launch (x -> out, device, total*nrhs each,
+ * distinct) for every candidate launch configuration -- workgroups per CU
+ * {occupancy, 1, 2, 3} x XCD order {1, 0} x tile schedule {plain, Morton
+ * over 2 or 3 prefix modes} -- with HIP events on the stream, and applies the
+ * fastest to the basis.  With cache_path (text file, may be NULL) a result
+ * keyed by (GPU architecture, CU count, M, nrhs, sectors, states, Nmax) is
+ * reused and new results are appended.  chosen[4] (host, may be NULL)
+ * receives {blocks_per_cu, xcd_order, tile_order, prefix_modes}, *best_ms the
+ * launch time.  Overwrites out. */
+fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c64* x, fh_c64* out,
+                            const char* cache_path, int* chosen, double* best_ms, void* stream);
 
 /* ---------------------------------------------------------------- adjoint --
  * Discrete adjoint of nsteps RK4 steps from psi0 (device), for the objective

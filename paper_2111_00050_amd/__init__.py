@@ -24,7 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libfockhip.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"libfockhip.so not found at {LIB_PATH}; build it with `python -m paper_2111_00050_amd.build`"
+        f"libfockhip.so not found at {LIB_PATH}; build it with `python paper_2111_00050_amd/build.py`"
     )
 
 _lib = ctypes.CDLL(LIB_PATH)
@@ -63,6 +63,7 @@ SIGNATURES = {
     "fh_basis_occupations": (_I, [_P, _P, _P]),
     "fh_basis_set_launch": (_I, [_P, _I, _I]),
     "fh_basis_set_tile_order": (_I, [_P, _I, _I]),
+    "fh_basis_autotune": (_I, [_P, _P, _I, _P, _P, ctypes.c_char_p, _P, _P, _P]),
     "fh_init_number": (_I, [_P, _P, _I, _P, _P]),
     "fh_init_coherent": (_I, [_P, _P, _I, _P, _P]),
     "fh_init_fieldnumber": (_I, [_P, _P, _I, _P, _P]),
@@ -141,7 +142,8 @@ class Model:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None):
+        # at interpreter shutdown the module globals may already be gone
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.fh_model_destroy(self._h)
             self._h = None
 
@@ -172,7 +174,7 @@ class Basis:
         return self._h
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.fh_basis_destroy(self._h)
             self._h = None
 
@@ -272,6 +274,22 @@ def apply_h(model, basis, psi, out=None):
     _check(_lib.fh_apply_h(model.handle, basis.handle, nrhs, _dev_ptr(psi, torch.complex128, "psi"),
                            _dev_ptr(out, torch.complex128, "out"), _stream()))
     return out
+
+
+def autotune(model, basis, x, cache_path=None):
+    """Pick the fastest launch configuration for H psi on this basis (fh_basis_autotune).
+    Returns ({blocks_per_cu, xcd_order, tile_order, prefix_modes}, milliseconds)."""
+    torch = _torch()
+    nrhs = _nrhs_of(basis, x)
+    out = torch.empty_like(x)
+    cfg = np.zeros(4, np.intc)
+    ms = np.zeros(1)
+    _check(_lib.fh_basis_autotune(model.handle, basis.handle, nrhs, _dev_ptr(x, torch.complex128, "x"),
+                                  _dev_ptr(out, torch.complex128, "out"),
+                                  None if cache_path is None else str(cache_path).encode(), _np_ptr(cfg), _np_ptr(ms),
+                                  _stream()))
+    keys = ("blocks_per_cu", "xcd_order", "tile_order", "prefix_modes")
+    return dict(zip(keys, (int(v) for v in cfg))), float(ms[0])
 
 
 def moments(basis, psi, rhs=0):

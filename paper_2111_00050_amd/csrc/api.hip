@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <complex>
@@ -291,7 +293,8 @@ fh_status make_basis(int M, int pmod, int nsec, const int32_t* N, const int32_t*
             b->tiles.push_back(Tile{s, (int)r, (int)std::min<int64_t>(kTileRows, b->dim[s] - r), 0});
     }
     b->tile_begin[nsec] = (int)b->tiles.size();
-    if (b->tiles.size() > (size_t)INT32_MAX) {
+    // the stage kernel walks up to 4 passes per tile in int arithmetic
+    if (b->tiles.size() > (size_t)INT32_MAX / 4) {
         delete b;
         set_error("fh_basis_create: too many tiles");
         return FH_EOVERFLOW;
@@ -451,6 +454,7 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
     const int slot = nrhs_slot(nrhs);
     const void* fn = b->ks->stage_fn[slot];
     const size_t lds = lds_bytes(b, 0);
+    const int G = stage_lanes_per_row(nrhs);  // workgroup passes per tile
     if (tm) {
         fh_status st = tm->begin();
         if (st != FH_OK) return st;
@@ -461,14 +465,14 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
             if (nt == 0) continue;
             a.tiles = b->d_tiles + b->tile_begin[sec];
             a.ntiles = nt;
-            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt), lds, s);
+            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
         }
     } else {
         const int nt = (int)b->tiles.size();
         if (nt > 0) {
             a.tiles = b->d_tiles;
             a.ntiles = nt;
-            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt), lds, s);
+            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
         }
     }
     FH_HIP(hipGetLastError());
@@ -683,6 +687,8 @@ fh_status fh_basis_set_tile_order(fh_basis* b, int order, int prefix_modes) {
         }
         b->tiles.swap(tiles);
         b->tile_begin.swap(begin);
+        b->tile_order = order;
+        b->prefix_modes = prefix_modes;
         (void)M;
         if (!b->tiles.empty())
             FH_HIP(hipMemcpy(b->d_tiles, b->tiles.data(), sizeof(Tile) * b->tiles.size(), hipMemcpyHostToDevice));
@@ -843,6 +849,101 @@ fh_status fh_apply_h(const fh_model* m, const fh_basis* b, int nrhs, const fh_c6
         a.out = reinterpret_cast<double*>(out);
         a.mode = kApply;
         return launch_stage(b, nrhs, a, 0, as_stream(stream), nullptr);
+    });
+}
+
+fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c64* x, fh_c64* out,
+                            const char* cache_path, int* chosen, double* best_ms, void* stream) {
+    return Guard::run([&]() -> fh_status {
+        if (!check_model_basis(m, b)) return FH_EINVAL;
+        FH_REQUIRE(!bad_nrhs(nrhs), FH_EINVAL, "nrhs must be 1, 2, 4, 8 or 16");
+        FH_REQUIRE(x != nullptr && out != nullptr && (const void*)x != (const void*)out, FH_EINVAL,
+                   "fh_basis_autotune: need distinct x and out buffers");
+        hipStream_t s = as_stream(stream);
+        hipDeviceProp_t prop;
+        FH_HIP(hipGetDeviceProperties(&prop, b->device));
+        const std::string key = std::string(prop.gcnArchName) + "/cu" + std::to_string(b->num_cu) + "/M" +
+                                std::to_string(b->M) + "/nrhs" + std::to_string(nrhs) + "/sec" +
+                                std::to_string(b->nsec) + "/states" + std::to_string(b->total) + "/Nmax" +
+                                std::to_string(b->Nmax);
+        int cfg[4] = {0, 1, 0, 0};  // blocks per CU, XCD order, tile order, prefix modes
+        double best = -1.0;
+        bool cached = false;
+        if (cache_path) {
+            if (FILE* f = std::fopen(cache_path, "r")) {
+                char line[512];
+                while (std::fgets(line, sizeof line, f)) {
+                    char k[400];
+                    int c0, c1, c2, c3;
+                    double ms;
+                    if (std::sscanf(line, "%399s %d %d %d %d %lf", k, &c0, &c1, &c2, &c3, &ms) == 6 && key == k) {
+                        cfg[0] = c0; cfg[1] = c1; cfg[2] = c2; cfg[3] = c3;
+                        best = ms;
+                        cached = true;
+                    }
+                }
+                std::fclose(f);
+            }
+        }
+        StageArgs a = stage_base(m, b);
+        a.x = reinterpret_cast<const double*>(x);
+        a.out = reinterpret_cast<double*>(out);
+        a.mode = kApply;
+        auto apply_cfg = [&](const int* c) -> fh_status {
+            b->blocks_per_cu = c[0];
+            b->xcd_order = c[1];
+            if (b->tile_order != c[2] || b->prefix_modes != c[3]) return fh_basis_set_tile_order(b, c[2], c[3]);
+            return FH_OK;
+        };
+        if (!cached) {
+            hipEvent_t e0, e1;
+            FH_HIP(hipEventCreate(&e0));
+            FH_HIP(hipEventCreate(&e1));
+            std::vector<std::array<int, 4>> cands;
+            const int maxp = std::min(b->M - 1, 3);
+            for (int bpc : {0, 1, 2, 3})
+                for (int xo : {1, 0})
+                    for (int pre = 0; pre <= maxp; ++pre) {
+                        if (pre == 1) continue;  // a one-mode prefix never pays
+                        cands.push_back({bpc, xo, pre > 0 ? 1 : 0, pre});
+                    }
+            fh_status st = FH_OK;
+            for (const auto& c : cands) {
+                if ((st = apply_cfg(c.data())) != FH_OK) break;
+                StageArgs ac = a;
+                ac.xcd_order = b->xcd_order;
+                if ((st = launch_stage(b, nrhs, ac, 0, s, nullptr)) != FH_OK) break;  // warm-up
+                float t = 0.f, tmin = 1e30f;
+                const int reps = best > 50.0 ? 1 : 3;
+                for (int r = 0; r < reps; ++r) {
+                    FH_HIP(hipEventRecord(e0, s));
+                    if ((st = launch_stage(b, nrhs, ac, 0, s, nullptr)) != FH_OK) break;
+                    FH_HIP(hipEventRecord(e1, s));
+                    FH_HIP(hipEventSynchronize(e1));
+                    FH_HIP(hipEventElapsedTime(&t, e0, e1));
+                    tmin = std::min(tmin, t);
+                }
+                if (st != FH_OK) break;
+                if (best < 0 || tmin < best) {
+                    best = tmin;
+                    std::copy(c.begin(), c.end(), cfg);
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            if (st != FH_OK) return st;
+            if (cache_path) {
+                if (FILE* f = std::fopen(cache_path, "a")) {
+                    std::fprintf(f, "%s %d %d %d %d %.6f\n", key.c_str(), cfg[0], cfg[1], cfg[2], cfg[3], best);
+                    std::fclose(f);
+                }
+            }
+        }
+        fh_status st = apply_cfg(cfg);
+        if (st != FH_OK) return st;
+        if (chosen) std::copy(cfg, cfg + 4, chosen);
+        if (best_ms) *best_ms = best;
+        return FH_OK;
     });
 }
 

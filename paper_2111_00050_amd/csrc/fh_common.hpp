@@ -31,6 +31,9 @@ constexpr int kMaxM = 10;
 constexpr int kTileRows = 256;  // one row per thread, four wave64s per workgroup
 constexpr int kRBias = 2;       // rank table rows R = -2 .. Nmax+2
 constexpr int kGatherBatch = 16;  // neighbour gathers issued together per thread
+// Lanes of the stage kernel that share one row when several right-hand sides
+// are evolved together; a workgroup then covers a tile in that many passes.
+constexpr FH_HD int stage_lanes_per_row(int nrhs) { return nrhs >= 4 ? 4 : nrhs; }
 #ifndef FH_STAGE_BLOCKS_PER_CU
 #define FH_STAGE_BLOCKS_PER_CU 1
 #endif

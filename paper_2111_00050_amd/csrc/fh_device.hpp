@@ -76,8 +76,10 @@ constexpr int move_offset(int s, int add0, int add1, int rem0, int rem1) {
 // Unrank row r of sector (N, P) with the table in LDS.
 //   D_{m+1}(R', Q') = T_{m+2}(R' + 1, Q' + m + 1)     for m + 1 <= M - 2
 //   D_{M-1}(R', Q') = [(M - 1) R' == Q' (mod M)]
-template <int M>
-__device__ __forceinline__ void unrank_row(const int* sT, int Rdim, int N, int P, int r, int (&n)[M]) {
+// With SC > 1 the table holds SC * T and r is SC times the row (unsigned, so
+// that sector offsets up to 2^32 stay exact).
+template <int M, unsigned SC = 1>
+__device__ __forceinline__ void unrank_row(const int* sT, int Rdim, int N, int P, unsigned r, int (&n)[M]) {
     constexpr int P2 = 2 * M;
     int R = N, Q = P;
 #pragma unroll
@@ -85,11 +87,11 @@ __device__ __forceinline__ void unrank_row(const int* sT, int Rdim, int N, int P
         int v = 0;
         while (v < R) {
             const int q = modM<M>(Q - m * v);
-            int cnt;
+            unsigned cnt;
             if (m + 1 <= M - 2) {
-                cnt = sT[(m + 1) * Rdim * P2 + (R - v + 1 + kRBias) * P2 + modM<M>(q + m + 1)];
+                cnt = (unsigned)sT[(m + 1) * Rdim * P2 + (R - v + 1 + kRBias) * P2 + modM<M>(q + m + 1)];
             } else {
-                cnt = (modM<M>((M - 1) * (R - v)) == q) ? 1 : 0;
+                cnt = (modM<M>((M - 1) * (R - v)) == q) ? SC : 0u;
             }
             if (r < cnt) break;
             r -= cnt;
@@ -104,8 +106,8 @@ __device__ __forceinline__ void unrank_row(const int* sT, int Rdim, int N, int P
 
 // key[s] (s >= 1): table index of T_s at the row's own suffix sums.
 // C[x] = sum_{s=1}^{x} T_s(R_s, Q_s), C[0] = 0.
-template <int M>
-__device__ __forceinline__ void row_keys(const int* sT, int Rdim, const int (&n)[M], int (&key)[M], int (&C)[M]) {
+template <int M, typename CT = int>
+__device__ __forceinline__ void row_keys(const int* sT, int Rdim, const int (&n)[M], int (&key)[M], CT (&C)[M]) {
     constexpr int P2 = 2 * M;
     int Rs[M], Qs[M];
     int R = 0, Q = 0;
@@ -121,7 +123,7 @@ __device__ __forceinline__ void row_keys(const int* sT, int Rdim, const int (&n)
 #pragma unroll
     for (int s = 1; s < M; ++s) {
         key[s] = (s - 1) * Rdim * P2 + Rs[s] * P2 + Qs[s];
-        C[s] = C[s - 1] + sT[key[s] + kRBias * P2];
+        C[s] = C[s - 1] + (CT)sT[key[s] + kRBias * P2];
     }
 }
 
@@ -172,8 +174,10 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double* red, double* 
     __syncthreads();
 }
 
+// Copy the rank table (times SC) and the square-root table into LDS.
+template <unsigned SC = 1>
 __device__ __forceinline__ void stage_tables(const int* T, int Tn, const double* sq, int nsq, int* sT, double* sSq) {
-    for (int q = threadIdx.x; q < Tn; q += blockDim.x) sT[q] = T[q];
+    for (int q = threadIdx.x; q < Tn; q += blockDim.x) sT[q] = (int)((unsigned)T[q] * SC);
     for (int q = threadIdx.x; q < nsq; q += blockDim.x) sSq[q] = sq[q];
     __syncthreads();
 }
@@ -187,21 +191,56 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
     extern __shared__ int smem[];
     int* sT = smem;
     double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
-    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+    // With one right-hand side the rank table is staged times 16, so that
+    // neighbour ranks come out directly as byte offsets into the sector.
+    constexpr unsigned SC = NRHS == 1 ? 16u : 1u;
+    stage_tables<SC>(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
 
-    const double* __restrict__ cf = A.coef;
+    // The coefficients are read-only for the whole launch and the same for
+    // every lane: read them through the constant address space so that they
+    // become scalar loads instead of one vector-memory pass per lane.
+    const __attribute__((address_space(4))) double* cf =
+        (const __attribute__((address_space(4))) double*)A.coef;
     const double2* X = reinterpret_cast<const double2*>(A.x);
     const int vb = virtual_block(A.xcd_order);
-    for (int t = vb; t < A.ntiles; t += gridDim.x) {
-        const Tile tl = A.tiles[t];
-        if ((int)threadIdx.x >= tl.nrows) continue;
-        const SecInfo sc = A.secs[tl.sec];
-        const int row = tl.row0 + (int)threadIdx.x;
+    // With several right-hand sides, G lanes share a row and lane `sub` owns
+    // the right-hand sides sub, sub + G, ...: every gather instruction then
+    // reads 16*G contiguous bytes per row.  The row's index work is repeated
+    // by its G lanes; its cost per right-hand side still falls as 1/NR.  A
+    // workgroup then takes one G-th of a tile at a time.
+    constexpr int G = stage_lanes_per_row(NRHS);
+    constexpr int NR = NRHS / G;
+    static_assert(NRHS % G == 0 && kTileRows % G == 0, "lanes per row must divide the tile");
+    const int sub = (int)threadIdx.x % G;
+    // Tile and sector descriptors are uniform over the workgroup: read them
+    // into SGPRs, so that every gather is an SGPR sector base plus a 32-bit
+    // lane offset.
+    const __attribute__((address_space(4))) Tile* tiles = (const __attribute__((address_space(4))) Tile*)A.tiles;
+    const __attribute__((address_space(4))) SecInfo* secs =
+        (const __attribute__((address_space(4))) SecInfo*)A.secs;
+    for (int vt = vb; vt < A.ntiles * G; vt += gridDim.x) {
+        const int tsec = __builtin_amdgcn_readfirstlane(tiles[vt / G].sec);
+        const int row0 = __builtin_amdgcn_readfirstlane(tiles[vt / G].row0);
+        const int nrows = __builtin_amdgcn_readfirstlane(tiles[vt / G].nrows);
+        SecInfo sc;
+        sc.N = __builtin_amdgcn_readfirstlane(secs[tsec].N);
+        sc.P = __builtin_amdgcn_readfirstlane(secs[tsec].P);
+        {
+            const unsigned long long o = (unsigned long long)secs[tsec].off;
+            const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)o);
+            const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(o >> 32));
+            sc.off = (long long)(((unsigned long long)hi << 32) | lo);
+        }
+        const int lrow = (vt % G) * (kTileRows / G) + (int)threadIdx.x / G;
+        if (lrow >= nrows) continue;
+        const int row = row0 + lrow;
 
+        const unsigned rowS = (unsigned)row * SC;
         int n[M];
-        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
-        int key[M], C[M];
-        row_keys<M>(sT, A.Rdim, n, key, C);
+        unrank_row<M, SC>(sT, A.Rdim, sc.N, sc.P, rowS, n);
+        int key[M];
+        unsigned C[M];
+        row_keys<M, unsigned>(sT, A.Rdim, n, key, C);
         double sq[M], sqp[M];
 #pragma unroll
         for (int s = 0; s < M; ++s) {
@@ -220,37 +259,49 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
 
         const long long soff = sc.off;
         const double2* xs = X + soff * NRHS;
-        double2 acc[NRHS];
+        double2 acc[NR];
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) acc[q] = make_double2(0.0, 0.0);
+        for (int q = 0; q < NR; ++q) acc[q] = make_double2(0.0, 0.0);
 
-        if constexpr (NRHS == 1) {
-            // One momentum class at a time, in chunks of up to kGatherBatch
+        {
+            // One momentum class at a time, in chunks of kGatherBatch / NR
             // combinations: all neighbour ranks first, then every gather of the
-            // chunk in flight together, then the FMAs.  Lanes whose row pair
-            // cannot be annihilated (c_ij == 0) gather their own row with a
-            // zero weight, so the chunk is straight-line code.
+            // chunk in flight together, then the FMAs.  For each row pair the
+            // source terms W c_kl x are summed first and scaled by c_ij once.
+            // Lanes whose row pair cannot be annihilated (c_ij == 0) gather
+            // their own row and scale it by zero, so the chunk is straight-line
+            // code.  Every NRHS sums each column in the same order.
             const char* xb = reinterpret_cast<const char*>(xs);
             static_for<0, M>([&](auto Cc) {
                 constexpr int c = decltype(Cc)::value;
                 constexpr int S = CB::class_size(c);
                 if constexpr (S > 1) {
                     constexpr int NQ = S * (S - 1);
-                    double cij[S];
+                    double cij[S], ckl[S];
                     static_for<0, S>([&](auto R1) {
                         constexpr int r1 = decltype(R1)::value;
                         constexpr int p1 = CB::class_member(c, r1);
                         constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
-                        // sqrt(n_i (n_j - d_ij)); zero exactly when the pair is empty
-                        if constexpr (i == j) cij[r1] = sq[i] * sSq[n[i] > 0 ? n[i] - 1 : 0];
-                        else cij[r1] = sq[i] * sq[j];
+                        // as the row pair: sqrt(n_i (n_j - d_ij)), zero exactly
+                        // when the pair is empty; as the source pair:
+                        // sqrt((n_i + 1)(n_j + 1 + d_ij))
+                        if constexpr (i == j) {
+                            cij[r1] = sq[i] * sSq[n[i] > 0 ? n[i] - 1 : 0];
+                            ckl[r1] = sqp[i] * sSq[n[i] + 2];
+                        } else {
+                            cij[r1] = sq[i] * sq[j];
+                            ckl[r1] = sqp[i] * sqp[j];
+                        }
                     });
-                    constexpr int QB = kGatherBatch;
+                    double2 pacc[NR];  // source sum of the current row pair
+                    constexpr int QB = kGatherBatch / NR;
                     constexpr int NCH = (NQ + QB - 1) / QB;
                     static_for<0, NCH>([&](auto Ch) {
                         constexpr int q0 = decltype(Ch)::value * QB;
                         constexpr int NQC = (NQ - q0) < QB ? (NQ - q0) : QB;
-                        unsigned off[NQC];
+                        // byte offset (one rhs) or element index (several)
+                        using off_t = std::conditional_t<NRHS == 1, unsigned, long long>;
+                        off_t off[NQC];
                         static_for<0, NQC>([&](auto Q) {
                             constexpr int q = q0 + decltype(Q)::value;
                             constexpr int r1 = q / (S - 1), t = q % (S - 1), r2 = t < r1 ? t : t + 1;
@@ -259,27 +310,47 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
                             constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
                             constexpr int lo = i < k ? i : k;
                             constexpr int hi = j > l ? j : l;
-                            int r = row + (C[hi] - C[lo]);
+                            unsigned r = rowS + (C[hi] - C[lo]);
                             static_for<lo + 1, hi + 1>([&](auto Sx) {
                                 constexpr int s = decltype(Sx)::value;
-                                r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
+                                r -= (unsigned)sT[key[s] + move_offset<M>(s, k, l, i, j)];
                             });
-                            off[decltype(Q)::value] = (unsigned)(cij[r1] != 0.0 ? r : row) * 16u;
+                            const unsigned src = cij[r1] != 0.0 ? r : rowS;
+                            if constexpr (NRHS == 1) off[decltype(Q)::value] = src;
+                            else off[decltype(Q)::value] = (long long)src * NRHS + sub;
                         });
-                        double2 v[NQC];
+                        double2 v[NQC][NR];
                         static_for<0, NQC>([&](auto Q) {
-                            v[decltype(Q)::value] = *reinterpret_cast<const double2*>(xb + off[decltype(Q)::value]);
+                            if constexpr (NRHS == 1) {
+                                v[decltype(Q)::value][0] =
+                                    *reinterpret_cast<const double2*>(xb + off[decltype(Q)::value]);
+                            } else {
+                                const double2* sp = xs + off[decltype(Q)::value];
+#pragma unroll
+                                for (int j = 0; j < NR; ++j) v[decltype(Q)::value][j] = sp[j * G];
+                            }
                         });
                         static_for<0, NQC>([&](auto Q) {
                             constexpr int q = q0 + decltype(Q)::value;
                             constexpr int r1 = q / (S - 1), t = q % (S - 1), r2 = t < r1 ? t : t + 1;
                             constexpr int p1 = CB::class_member(c, r1), p2 = CB::class_member(c, r2);
-                            constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
                             constexpr int ci = M + NP + CB::index(p1, p2);
-                            const double ckl = (k == l) ? sqp[k] * sSq[n[k] + 2] : sqp[k] * sqp[l];
-                            const double w = cf[ci] * (cij[r1] * ckl);
-                            acc[0].x = fma(w, v[decltype(Q)::value].x, acc[0].x);
-                            acc[0].y = fma(w, v[decltype(Q)::value].y, acc[0].y);
+                            const double w = cf[ci] * ckl[r2];
+#pragma unroll
+                            for (int j = 0; j < NR; ++j) {
+                                const double2 x = v[decltype(Q)::value][j];
+                                if constexpr (t == 0) {
+                                    pacc[j].x = w * x.x;
+                                    pacc[j].y = w * x.y;
+                                } else {
+                                    pacc[j].x = fma(w, x.x, pacc[j].x);
+                                    pacc[j].y = fma(w, x.y, pacc[j].y);
+                                }
+                                if constexpr (t == S - 2) {
+                                    acc[j].x = fma(cij[r1], pacc[j].x, acc[j].x);
+                                    acc[j].y = fma(cij[r1], pacc[j].y, acc[j].y);
+                                }
+                            }
                         });
                         // Keep chunks apart: no table read is reused across them
                         // and the scheduler does not interleave their gathers,
@@ -289,61 +360,24 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
                     });
                 }
             });
-        } else {
-            // Several right-hand sides: each neighbour is one contiguous run
-            // of NRHS amplitudes, already NRHS loads in flight per gather.
-            static_for<0, NP>([&](auto P1) {
-                constexpr int p1 = decltype(P1)::value;
-                constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
-                if constexpr (CB::class_size(CB::cls(p1)) > 1) {
-                    const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
-                    if (valid) {
-                        const double cij = (i == j) ? sq[i] * sSq[n[i] - 1] : sq[i] * sq[j];
-                        double2 pacc[NRHS];
+        }
+        // Pin the accumulators here: otherwise the compiler sinks each
+        // column's FMA chain into the mode branches below (its only users)
+        // and keeps every gathered amplitude alive until then.
+        if constexpr (NR > 1) {
 #pragma unroll
-                        for (int q = 0; q < NRHS; ++q) pacc[q] = make_double2(0.0, 0.0);
-                        static_for<0, NP>([&](auto P2) {
-                            constexpr int p2 = decltype(P2)::value;
-                            if constexpr (CB::linked(p1, p2)) {
-                                constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
-                                constexpr int ci = M + NP + CB::index(p1, p2);
-                                constexpr int lo = i < k ? i : k;
-                                constexpr int hi = j > l ? j : l;
-                                int r = row + (C[hi] - C[lo]);
-                                static_for<lo + 1, hi + 1>([&](auto Sx) {
-                                    constexpr int s = decltype(Sx)::value;
-                                    r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
-                                });
-                                const double ckl = (k == l) ? sqp[k] * sSq[n[k] + 2] : sqp[k] * sqp[l];
-                                const double w = cf[ci] * ckl;
-                                const double2* src = xs + (long long)r * NRHS;
-#pragma unroll
-                                for (int q = 0; q < NRHS; ++q) {
-                                    const double2 v = src[q];
-                                    pacc[q].x = fma(w, v.x, pacc[q].x);
-                                    pacc[q].y = fma(w, v.y, pacc[q].y);
-                                }
-                            }
-                        });
-#pragma unroll
-                        for (int q = 0; q < NRHS; ++q) {
-                            acc[q].x = fma(cij, pacc[q].x, acc[q].x);
-                            acc[q].y = fma(cij, pacc[q].y, acc[q].y);
-                        }
-                    }
-                }
-            });
+            for (int q = 0; q < NR; ++q) asm volatile("" : "+v"(acc[q].x), "+v"(acc[q].y));
         }
 
-        const long long e = (soff + row) * NRHS;
 #pragma unroll
-        for (int q = 0; q < NRHS; ++q) {
-            const double2 xv = X[e + q];
+        for (int q = 0; q < NR; ++q) {
+            const long long e = (soff + row) * NRHS + (NRHS == 1 ? 0 : sub + q * G);
+            const double2 xv = X[e];
             double2 h1;
             h1.x = fma(diag, xv.x, acc[q].x);
             h1.y = fma(diag, xv.y, acc[q].y);
             if (A.mode == kApply) {
-                reinterpret_cast<double2*>(A.out)[e + q] = h1;
+                reinterpret_cast<double2*>(A.out)[e] = h1;
                 continue;
             }
             double2 kk;
@@ -353,14 +387,14 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
             // them past the caches (non-temporal) so that the gathered vector
             // keeps L2 and the memory-side cache.
             if (A.mode == kLast) {
-                const v2d ac = nt_load(A.acc + 2 * (e + q));
-                nt_store(A.baseout + 2 * (e + q), v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
+                const v2d ac = nt_load(A.acc + 2 * e);
+                nt_store(A.baseout + 2 * e, v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
                 continue;
             }
-            const v2d bs = nt_load(A.base + 2 * (e + q));
-            const v2d ac = (A.mode == kFirst) ? bs : nt_load(A.acc + 2 * (e + q));
-            nt_store(A.acc + 2 * (e + q), v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
-            reinterpret_cast<double2*>(A.ynext)[e + q] =
+            const v2d bs = nt_load(A.base + 2 * e);
+            const v2d ac = (A.mode == kFirst) ? bs : nt_load(A.acc + 2 * e);
+            nt_store(A.acc + 2 * e, v2d{fma(A.a, kk.x, ac.x), fma(A.a, kk.y, ac.y)});
+            reinterpret_cast<double2*>(A.ynext)[e] =
                 make_double2(fma(A.b, kk.x, A.c0 * bs.x), fma(A.b, kk.y, A.c0 * bs.y));
         }
     }

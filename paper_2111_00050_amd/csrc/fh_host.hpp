@@ -48,6 +48,8 @@ struct fh_basis {
     int grid_cap = 0;              // max persistent workgroups
     int blocks_per_cu = 0;         // 0 = occupancy limit
     int xcd_order = 1;
+    int tile_order = 0;            // fh_basis_set_tile_order
+    int prefix_modes = 0;
     const fh::KernelSet* ks = nullptr;
 
     int64_t D_at(int m, int R, int Q) const {

@@ -94,19 +94,18 @@ def test_apply_h_vs_oracle(M, sectors, kind):
     assert _rel(got, want) <= 1e-13
 
 
-@pytest.mark.parametrize("nrhs", [2, 4, 8, 16])
-def test_apply_h_multi_rhs(nrhs):
-    M = 6
-    sectors = [(9, p) for p in range(M)]
+@pytest.mark.parametrize("M,nrhs", [(6, 2), (6, 4), (6, 8), (6, 16), (8, 8), (10, 16)])
+def test_apply_h_multi_rhs(M, nrhs):
+    Nmax = {6: 9, 8: 6, 10: 4}[M]
+    sectors = [(Nmax, p) for p in range(M)] + [(Nmax - 1, 1)]
     omega, V = _model("longrange", M, 3)
     orc, model, b = _pair(M, sectors, omega, 0.21, V)
     X = W.random_psi(orc.total, 17, nrhs=nrhs)
     got = fh.apply_h(model, b, torch.from_numpy(X).cuda()).cpu().numpy()
     for q in range(nrhs):
-        # the multi-rhs kernel sums each row pair first, the single-rhs one
-        # sums class by class: equal up to rounding of the same terms
+        # every column is summed in the single-rhs order: bitwise equal
         single = fh.apply_h(model, b, torch.from_numpy(np.ascontiguousarray(X[:, q])).cuda()).cpu().numpy()
-        assert _rel(got[:, q], single) <= 1e-14
+        assert np.array_equal(got[:, q], single)
         assert _rel(got[:, q], orc.apply_h(np.ascontiguousarray(X[:, q]))) <= 1e-13
 
 
