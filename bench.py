@@ -87,12 +87,142 @@ def cpu_baseline(w, target_s: float = 15.0):
     }
 
 
+def forms():
+    """The three forms of the path next to their plain counterparts, each on
+    its own workload at full size with a bounded number of steps:
+      batched   : one persistent launch per stage over all sectors, the step
+                  captured in a HIP graph, vs one launch per sector per stage
+                  (M=6 coherent state, mean 40 bosons, 541 sectors);
+      multi_rhs : 16 field-number phase draws as one 16-column vector vs the
+                  same draws run one at a time (M=10, N=30, all 10 P);
+      adjoint   : forward + discrete adjoint (gradients of J) vs the forward
+                  alone (M=6 number state N=30, 3000 steps; M=6 coherent
+                  state, mean 20, 331 sectors, 100 steps), with a central
+                  difference of J in Lambda on the first.
+    Equal-accuracy check: the two paths of a pair return the same amplitudes
+    (max |difference| is reported; the kernels sum in the same order)."""
+    import numpy as np
+    import torch
+
+    import paper_2111_00050_amd as fh
+    import workloads as W
+
+    sync = torch.cuda.synchronize
+    c128 = torch.complex128
+
+    def log(msg):
+        print(f"[bench/forms] {msg}", file=sys.stderr, flush=True)
+
+    def timed(fn):
+        sync()
+        t0 = time.perf_counter()
+        r = fn()
+        sync()
+        return r, time.perf_counter() - t0
+
+    out = {}
+    # ---- batched vs per sector
+    w = W.batched_coherent()
+    model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    D = basis.total
+    log(f"batched: {D} states in {len(w.sectors)} sectors")
+    psi0 = fh.init_coherent(basis, w.init_params)
+    work = torch.empty(3 * D, dtype=c128, device="cuda")
+    steps, fin, sps = 3, {}, {}
+    stream = torch.cuda.Stream()  # graph capture needs a non-default stream
+    for name, flags in (("batched", fh.FH_GRAPH), ("per_sector", fh.FH_PER_SECTOR)):
+        psi = psi0.clone()
+        sync()
+        with torch.cuda.stream(stream):
+            fh.evolve_rk4(model, basis, psi, w.dt, 1, flags=flags, work=work)
+            _, t = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps, flags=flags, work=work))
+        sps[name], fin[name] = steps / t, psi
+        log(f"  {name}: {steps / t:.3f} steps/s")
+    out["batched"] = {
+        "workload": "M=6 coherent, mean 40 bosons, N 0..90 x all P, contact V, Lambda=0.05, dt=1e-3",
+        "states": D, "sectors": sum(1 for d in basis.dims if d > 0), "timed_steps": steps,
+        "steps_per_s": sps["batched"], "per_sector_steps_per_s": sps["per_sector"],
+        "speedup": sps["batched"] / sps["per_sector"],
+        "max_abs_diff": float((fin["batched"] - fin["per_sector"]).abs().max()),
+    }
+    del psi0, psi, work, fin
+    model.close()
+    basis.close()
+    torch.cuda.empty_cache()
+
+    # ---- 16 columns vs 16 single runs
+    w = W.fieldnumber_draws(16, 30)
+    model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    D = basis.total
+    log(f"multi-rhs: {D} states x 16 draws")
+    steps = 2
+    psi = fh.init_fieldnumber(basis, w.init_params)
+    work = torch.empty(3 * D * 16, dtype=c128, device="cuda")
+    fh.evolve_rk4(model, basis, psi, w.dt, 1, work=work)
+    _, tm = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps, work=work))
+    col0 = psi[:, 0].clone()
+    del psi, work
+    torch.cuda.empty_cache()
+    log(f"  16 columns: {steps / tm:.4f} steps/s")
+    psi1 = fh.init_fieldnumber(basis, w.init_params[0])
+    work1 = torch.empty(3 * D, dtype=c128, device="cuda")
+    fh.evolve_rk4(model, basis, psi1, w.dt, 1, work=work1)
+    _, ts = timed(lambda: fh.evolve_rk4(model, basis, psi1, w.dt, steps, work=work1))
+    log(f"  one column: {steps / ts:.4f} steps/s")
+    out["multi_rhs"] = {
+        "workload": "M=10 field-number states, 16 phase draws, N=30 x all 10 P, contact V, Lambda=0.01, dt=2e-4",
+        "states": D, "rhs": 16, "timed_steps": steps,
+        "steps_per_s_16_draws": steps / tm, "steps_per_s_16_draws_one_at_a_time": steps / ts / 16,
+        "speedup": 16 * ts / tm,
+        "max_abs_diff_draw0": float((psi1 - col0).abs().max()),
+    }
+    del psi1, work1, col0
+    model.close()
+    basis.close()
+    torch.cuda.empty_cache()
+
+    # ---- adjoint vs forward
+    adj = []
+    for w, obj, steps, ck in ((W.adjoint_number(30), fh.FH_J_NMODE, 3000, 100),
+                              (W.adjoint_coherent(20.0), fh.FH_J_Q, 100, 10)):
+        model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+        log(f"adjoint: {w.name}, {basis.total} states, {steps} steps")
+        init = (lambda b=basis, w=w: fh.init_number(b, w.init_params) if w.init == "number"
+                else fh.init_coherent(b, w.init_params))
+        psi = init()
+        _, tf = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps))
+        psi0 = init()
+        res, ta = timed(lambda: fh.adjoint_rk4(model, basis, psi0, w.dt, steps, ck, obj, 0))
+        rec = {"workload": w.name, "states": basis.total, "steps": steps, "checkpoint_every": ck,
+               "objective": {fh.FH_J_Q: "Q", fh.FH_J_NMODE: "<n_0>(T)"}[obj],
+               "forward_s": tf, "adjoint_s": ta, "ratio": ta / tf,
+               "J": float(res["J"][0]), "dJ_dLambda": float(res["dLambda"][0])}
+        if steps == 3000:
+            h = 1e-6
+            Jpm = []
+            for sgn in (1, -1):
+                mh = fh.Model(w.M, w.omega, w.Lambda + sgn * h, w.V)
+                Jpm.append(float(fh.adjoint_rk4(mh, basis, init(), w.dt, steps, ck, obj, 0)["J"][0]))
+                mh.close()
+            fd = (Jpm[0] - Jpm[1]) / (2 * h)
+            rec["dJ_dLambda_central_difference"] = fd
+        log(f"  ratio {ta / tf:.2f}")
+        adj.append(rec)
+        del psi, psi0, res
+        model.close()
+        basis.close()
+        torch.cuda.empty_cache()
+    out["adjoint"] = adj
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the batched / multi-rhs / adjoint comparisons")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--xcd-order", type=int, default=1)
     ap.add_argument("--tile-order", type=int, default=0)
@@ -173,6 +303,12 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle on a sample", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(w)
+    if not args.no_forms:
+        del psi, work
+        model.close()
+        basis.close()
+        torch.cuda.empty_cache()
+        line["forms"] = forms()
     print(json.dumps(line), flush=True)
 
 

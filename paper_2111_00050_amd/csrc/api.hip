@@ -230,6 +230,7 @@ void basis_free(fh_basis* b) {
     (void)hipFree(b->d_secmap);
     (void)hipFree(b->d_partial);
     (void)hipFree(b->d_small);
+    (void)hipFree(b->d_occ);
     delete b;
 }
 
@@ -335,6 +336,23 @@ fh_status make_basis(int M, int pmod, int nsec, const int32_t* N, const int32_t*
     if ((e = hipMemcpy(b->d_secmap, b->secmap.data(), sizeof(int) * b->secmap.size(), hipMemcpyHostToDevice)) !=
         hipSuccess)
         return fail(e, "hipMemcpy");
+    // occupation records (occ_stride(M) bytes per state), filled once here
+    if ((e = hipMalloc(&b->d_occ, (size_t)occ_stride(M) * std::max<int64_t>(1, b->total))) != hipSuccess)
+        return fail(e, "hipMalloc");
+    if (!b->tiles.empty()) {
+        OccArgs oa{};
+        oa.T = b->d_T;
+        oa.Tn = b->Tn;
+        oa.Rdim = b->Rdim;
+        oa.tiles = b->d_tiles;
+        oa.ntiles = (int)b->tiles.size();
+        oa.secs = b->d_secs;
+        oa.occ = b->d_occ;
+        const size_t lds = sizeof(int) * b->Tn;
+        b->ks->occ_table(oa, std::min(oa.ntiles, 4 * b->num_cu), lds, nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return fail(e, "occ_table_kernel");
+        if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+    }
     *out = b;
     return FH_OK;
 }
@@ -896,9 +914,16 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
             return FH_OK;
         };
         if (!cached) {
-            hipEvent_t e0, e1;
-            FH_HIP(hipEventCreate(&e0));
-            FH_HIP(hipEventCreate(&e1));
+            struct Events {  // destroyed on every return path
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                ~Events() {
+                    if (e0) (void)hipEventDestroy(e0);
+                    if (e1) (void)hipEventDestroy(e1);
+                }
+            } ev;
+            FH_HIP(hipEventCreate(&ev.e0));
+            FH_HIP(hipEventCreate(&ev.e1));
+            hipEvent_t e0 = ev.e0, e1 = ev.e1;
             std::vector<std::array<int, 4>> cands;
             const int maxp = std::min(b->M - 1, 3);
             for (int bpc : {0, 1, 2, 3})
@@ -929,8 +954,6 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
                     std::copy(c.begin(), c.end(), cfg);
                 }
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
             if (st != FH_OK) return st;
             if (cache_path) {
                 if (FILE* f = std::fopen(cache_path, "a")) {
@@ -1135,8 +1158,9 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* u, double
     a.secs = b->d_secs;
     a.partial = b->d_partial;
     a.xcd_order = b->xcd_order;
+    a.occ = b->d_occ;
     const int G = persistent_grid(b, b->ks->corr_fn, lds, nt);
-    b->ks->corr(a, G, M, lds, s);
+    b->ks->corr(a, G, M, lds, s);  // one row of workgroups per momentum class
     FH_HIP(hipGetLastError());
     launch_reduce_partials(b->d_partial, M, G, 2 * kCorrOutMax, 2 * kCorrOutMax, gtotal, 1, s);
     FH_HIP(hipGetLastError());

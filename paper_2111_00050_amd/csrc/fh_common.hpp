@@ -187,9 +187,22 @@ struct OneBodyArgs {
     const double* cf;   // c0(2), cN(2), u[M](2), v[M](2), h[M*M](2)
 };
 
+// Occupation records: the occupations of every state of a basis, one byte per
+// mode, padded to occ_stride(M) bytes, at the state's global index.
+constexpr FH_HD int occ_stride(int M) { return M <= 8 ? 8 : 16; }
+struct OccArgs {
+    const int* T;
+    int Tn, Rdim;
+    const Tile* tiles;
+    int ntiles;
+    const SecInfo* secs;
+    unsigned char* occ;
+};
+
 // Quartic correlators  G[c][(p1,p2)] = sum_n conj(u(n)) <n|a_i^+ a_j^+ a_k a_l|n'> y(n')
 // for pairs p1 = {i,j}, p2 = {k,l} of class c (p1 == p2 included).
 struct CorrArgs {
+    const unsigned char* occ;  // occupation records
     const double* u;
     const double* y;
     double uscale;      // u is used as uscale * u

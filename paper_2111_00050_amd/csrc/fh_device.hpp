@@ -574,15 +574,58 @@ __global__ __launch_bounds__(kTileRows) void onebody_kernel(OneBodyArgs A) {
 }
 
 // ------------------------------------------------------- correlators -----
-// G[class][r1 * S + r2] += sum_n conj(uscale u(n)) <n| a_i^+ a_j^+ a_k a_l |n'> y(n')
-// p1 = member(class, r1) = {i,j}, p2 = member(class, r2) = {k,l},
-// n' = n - e_i - e_j + e_k + e_l.
+// Occupations of a state from its record (occ_stride(M) bytes).
 template <int M>
-__global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
+__device__ __forceinline__ void load_occ(const unsigned char* occ, long long state, int (&n)[M]) {
+    if constexpr (M <= 8) {
+        const uint2 w = reinterpret_cast<const uint2*>(occ)[state];
+#pragma unroll
+        for (int m = 0; m < M; ++m) n[m] = (int)(((m < 4 ? w.x : w.y) >> (8 * (m & 3))) & 0xffu);
+    } else {
+        const uint4 w = reinterpret_cast<const uint4*>(occ)[state];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const unsigned v = m < 4 ? w.x : m < 8 ? w.y : m < 12 ? w.z : w.w;
+            n[m] = (int)((v >> (8 * (m & 3))) & 0xffu);
+        }
+    }
+}
+
+// Fill the occupation records of every state (unrank once per state).
+template <int M>
+__global__ __launch_bounds__(kTileRows) void occ_table_kernel(OccArgs A) {
+    extern __shared__ int smem[];
+    int* sT = smem;
+    for (int q = threadIdx.x; q < A.Tn; q += blockDim.x) sT[q] = A.T[q];
+    __syncthreads();
+    for (int t = blockIdx.x; t < A.ntiles; t += gridDim.x) {
+        const Tile tl = A.tiles[t];
+        if ((int)threadIdx.x >= tl.nrows) continue;
+        const SecInfo sc = A.secs[tl.sec];
+        const int row = tl.row0 + (int)threadIdx.x;
+        int n[M];
+        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        unsigned w[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int m = 0; m < M; ++m) w[m >> 2] |= (unsigned)n[m] << (8 * (m & 3));
+        const long long state = sc.off + row;
+        if constexpr (M <= 8) reinterpret_cast<uint2*>(A.occ)[state] = make_uint2(w[0], w[1]);
+        else reinterpret_cast<uint4*>(A.occ)[state] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// G[r1 * S + r2] += sum_n conj(uscale u(n)) <n| a_i^+ a_j^+ a_k a_l |n'> y(n')
+// for the pairs p1 = member(C, r1) = {i,j}, p2 = member(C, r2) = {k,l} of one
+// momentum class C, n' = n - e_i - e_j + e_k + e_l (n' = n when r1 == r2).
+// One body per class keeps exactly that class's S^2 complex sums in
+// registers across the persistent tile loop; rows start from their
+// occupation records.  Partials are written with row stride max_class_size.
+template <int M, int C>
+__device__ __forceinline__ void corr_class(const CorrArgs& A) {
     using CB = Combos<M>;
-    constexpr int NP = CB::NP;
+    constexpr int S = CB::class_size(C);
     constexpr int SMAX = CB::max_class_size();
-    constexpr int NV = 2 * SMAX * SMAX;
+    constexpr int NV = 2 * S * S;
     extern __shared__ int smem[];
     int* sT = smem;
     double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
@@ -591,7 +634,6 @@ __global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
     const double2* __restrict__ U = reinterpret_cast<const double2*>(A.u);
     const double2* __restrict__ Y = reinterpret_cast<const double2*>(A.y);
     const int nrhs = A.nrhs, rhs = A.rhs;
-    const int cls = blockIdx.y;
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
@@ -601,58 +643,101 @@ __global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
         if ((int)threadIdx.x >= tl.nrows) continue;
         const SecInfo sc = A.secs[tl.sec];
         const int row = tl.row0 + (int)threadIdx.x;
+        const long long state = sc.off + row;
         int n[M];
-        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
-        int key[M], C[M];
-        row_keys<M>(sT, A.Rdim, n, key, C);
-        double2 u = U[(sc.off + row) * nrhs + rhs];
+        load_occ<M>(A.occ, state, n);
+        int key[M], Cs[M];
+        row_keys<M>(sT, A.Rdim, n, key, Cs);
+        double2 u = U[state * nrhs + rhs];
         u.x *= A.uscale;
         u.y *= A.uscale;
-        static_for<0, M>([&](auto Cc) {
-            constexpr int c = decltype(Cc)::value;
-            constexpr int S = CB::class_size(c);
-            if (cls == c) {
-                static_for<0, S>([&](auto R1) {
-                    constexpr int r1 = decltype(R1)::value;
-                    constexpr int p1 = CB::class_member(c, r1);
-                    constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
-                    const bool valid = (i == j) ? (n[i] >= 2) : (n[i] >= 1 && n[j] >= 1);
-                    if (valid) {
-                        const double cij = (i == j) ? sSq[n[i]] * sSq[n[i] - 1] : sSq[n[i]] * sSq[n[j]];
-                        static_for<0, S>([&](auto R2) {
-                            constexpr int r2 = decltype(R2)::value;
-                            constexpr int p2 = CB::class_member(c, r2);
-                            constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
-                            double2 y;
-                            double cc;
-                            if constexpr (p1 == p2) {
-                                y = Y[(sc.off + row) * nrhs + rhs];
-                                cc = cij * cij;
-                            } else {
-                                constexpr int lo = i < k ? i : k;
-                                constexpr int hi = j > l ? j : l;
-                                int r = row + (C[hi] - C[lo]);
-                                static_for<lo + 1, hi + 1>([&](auto Sx) {
-                                    constexpr int s = decltype(Sx)::value;
-                                    r -= sT[key[s] + move_offset<M>(s, k, l, i, j)];
-                                });
-                                y = Y[(sc.off + r) * nrhs + rhs];
-                                cc = cij * ((k == l) ? sSq[n[k] + 1] * sSq[n[k] + 2] : sSq[n[k] + 1] * sSq[n[l] + 1]);
-                            }
-                            constexpr int o = 2 * (r1 * SMAX + r2);
-                            acc[o] = fma(cc, u.x * y.x + u.y * y.y, acc[o]);
-                            acc[o + 1] = fma(cc, u.x * y.y - u.y * y.x, acc[o + 1]);
-                        });
-                    }
-                });
+        double cij[S], ckl[S];
+        static_for<0, S>([&](auto R1) {
+            constexpr int r1 = decltype(R1)::value;
+            constexpr int p1 = CB::class_member(C, r1);
+            constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+            if constexpr (i == j) {
+                cij[r1] = sSq[n[i]] * sSq[n[i] > 0 ? n[i] - 1 : 0];
+                ckl[r1] = sSq[n[i] + 1] * sSq[n[i] + 2];
+            } else {
+                cij[r1] = sSq[n[i]] * sSq[n[j]];
+                ckl[r1] = sSq[n[i] + 1] * sSq[n[j] + 1];
             }
         });
+        {
+            // p1 == p2: <n|a_i^+ a_j^+ a_i a_j|n> = c_ij^2
+            const double2 y = Y[state * nrhs + rhs];
+            const double tr = u.x * y.x + u.y * y.y, ti = u.x * y.y - u.y * y.x;
+            static_for<0, S>([&](auto R1) {
+                constexpr int r1 = decltype(R1)::value;
+                constexpr int o = 2 * (r1 * S + r1);
+                const double c2 = cij[r1] * cij[r1];
+                acc[o] = fma(c2, tr, acc[o]);
+                acc[o + 1] = fma(c2, ti, acc[o + 1]);
+            });
+        }
+        if constexpr (S > 1) {
+            // Off-diagonal pairs in chunks: neighbour ranks, then the gathers
+            // in flight together, then the sums.  Lanes whose row pair is
+            // empty (c_ij == 0) gather their own row and add zero.
+            constexpr int NQ = S * (S - 1);
+            constexpr int QB = S >= 5 ? kGatherBatch / 2 : kGatherBatch;
+            constexpr int NCH = (NQ + QB - 1) / QB;
+            static_for<0, NCH>([&](auto Ch) {
+                constexpr int q0 = decltype(Ch)::value * QB;
+                constexpr int NQC = (NQ - q0) < QB ? (NQ - q0) : QB;
+                long long off[NQC];
+                static_for<0, NQC>([&](auto Q) {
+                    constexpr int q = q0 + decltype(Q)::value;
+                    constexpr int r1 = q / (S - 1), tq = q % (S - 1), r2 = tq < r1 ? tq : tq + 1;
+                    constexpr int p1 = CB::class_member(C, r1), p2 = CB::class_member(C, r2);
+                    constexpr int i = CB::pairs.i[p1], j = CB::pairs.j[p1];
+                    constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
+                    constexpr int lo = i < k ? i : k;
+                    constexpr int hi = j > l ? j : l;
+                    int r = row + (Cs[hi] - Cs[lo]);
+                    static_for<lo + 1, hi + 1>([&](auto Sx) {
+                        constexpr int s2 = decltype(Sx)::value;
+                        r -= sT[key[s2] + move_offset<M>(s2, k, l, i, j)];
+                    });
+                    const int src = cij[r1] != 0.0 ? r : row;
+                    off[decltype(Q)::value] = (sc.off + src) * nrhs + rhs;
+                });
+                double2 v[NQC];
+                static_for<0, NQC>([&](auto Q) { v[decltype(Q)::value] = Y[off[decltype(Q)::value]]; });
+                static_for<0, NQC>([&](auto Q) {
+                    constexpr int q = q0 + decltype(Q)::value;
+                    constexpr int r1 = q / (S - 1), tq = q % (S - 1), r2 = tq < r1 ? tq : tq + 1;
+                    constexpr int o = 2 * (r1 * S + r2);
+                    const double2 y = v[decltype(Q)::value];
+                    const double w = cij[r1] * ckl[r2];
+                    acc[o] = fma(w, u.x * y.x + u.y * y.y, acc[o]);
+                    acc[o + 1] = fma(w, u.x * y.y - u.y * y.x, acc[o + 1]);
+                });
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            });
+        }
     }
-    __shared__ double outv[2 * kCorrOutMax];
+    __shared__ double outv[NV];
     block_sum<NV>(acc, red, outv);
-    if (threadIdx.x < NV) {
-        A.partial[((size_t)cls * gridDim.x + blockIdx.x) * 2 * kCorrOutMax + threadIdx.x] = outv[threadIdx.x];
+    if ((int)threadIdx.x < 2 * kCorrOutMax) {
+        const int part = threadIdx.x & 1, slot = threadIdx.x >> 1;
+        const int r1 = slot / SMAX, r2 = slot % SMAX;
+        const double v = (r1 < S && r2 < S) ? outv[2 * (r1 * S + r2) + part] : 0.0;
+        A.partial[((size_t)C * gridDim.x + blockIdx.x) * 2 * kCorrOutMax + threadIdx.x] = v;
     }
+}
+
+// All classes in one launch: blockIdx.y selects the class.  The branch is
+// uniform over the workgroup and each class body holds its own sums, so the
+// registers are those of the largest class, not of all of them.
+template <int M>
+__global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
+    static_for<0, M>([&](auto Cc) {
+        constexpr int c = decltype(Cc)::value;
+        if ((int)blockIdx.y == c) corr_class<M, c>(A);
+    });
 }
 
 // ------------------------------------------------------- initial states --

@@ -41,8 +41,9 @@ struct fh_basis {
     int* d_secmap = nullptr;
     double* d_partial = nullptr;   // reduction partials
     size_t partial_doubles = 0;
-    double* d_small = nullptr;     // reduced values, cofficient tables, ...
+    double* d_small = nullptr;     // reduced values, coefficient tables, ...
     size_t small_doubles = 0;
+    unsigned char* d_occ = nullptr;  // occupation record of every state (occ_stride(M) bytes)
     int device = 0;
     int num_cu = 0;
     int grid_cap = 0;              // max persistent workgroups

@@ -35,6 +35,7 @@ struct KernelSet {
     void (*onebody)(const OneBodyArgs&, int grid, size_t lds, hipStream_t);
     const void* corr_fn;
     void (*corr)(const CorrArgs&, int grid, int classes, size_t lds, hipStream_t);
+    void (*occ_table)(const OccArgs&, int grid, size_t lds, hipStream_t);
     void (*init_product)(const InitArgs&, int grid, size_t lds, hipStream_t);
     void (*vjp)(const VjpArgs&, int grid, size_t lds, hipStream_t);
     void (*rank)(const RankArgs&, hipStream_t);

@@ -25,6 +25,9 @@ void onebody_l(const OneBodyArgs& a, int grid, size_t lds, hipStream_t s) {
 void corr_l(const CorrArgs& a, int grid, int classes, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((corr_kernel<kM>), dim3(grid, classes), dim3(kTileRows), lds, s, a);
 }
+void occ_l(const OccArgs& a, int grid, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((occ_table_kernel<kM>), dim3(grid), dim3(kTileRows), lds, s, a);
+}
 void init_l(const InitArgs& a, int grid, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((init_product_kernel<kM>), dim3(grid), dim3(kTileRows), lds, s, a);
 }
@@ -60,6 +63,7 @@ const KernelSet* FH_CAT(kernel_set_M, FH_INST_M)() {
         &onebody_l,
         reinterpret_cast<const void*>(&corr_kernel<kM>),
         &corr_l,
+        &occ_l,
         &init_l,
         &vjp_l,
         &rank_l,

@@ -317,3 +317,51 @@ def test_adjoint_vs_oracle():
         wre, wim = evolve.coherent_alpha_gradient(orc, alpha, psi0o, ref["g0"])
         assert np.abs(dre[0] - wre).max() <= 1e-9 * max(1, np.abs(wre).max())
         assert np.abs(dim[0] - wim).max() <= 1e-9 * max(1, np.abs(wim).max())
+
+
+def test_qevolve_gradcheck():
+    """torch.autograd binding: its backward equals central differences of its
+    forward for Re alpha, Im alpha, Lambda and every momentum-conserving V
+    entry (the non-conserving ones are not parameters of the model)."""
+    from paper_2111_00050_amd.autograd import EvolveSpec, QEvolve
+
+    M = 3
+    b = fh.Basis(M, W.all_sectors(M, 8))
+    spec = EvolveSpec(b, W.omega_quadratic(M), 1e-2, 40, ckpt_every=9, objective=fh.FH_J_Q)
+    cons = torch.as_tensor(np.flatnonzero(W.V_contact(M).ravel() != 0))
+    V0 = (W.V_longrange(M) + 0.3 * W.V_contact(M)).ravel()
+    a = W.coherent_amplitudes(31, M, 1.2)
+    f64 = dict(dtype=torch.float64, requires_grad=True)
+    are, aim = torch.tensor(a.real, **f64), torch.tensor(a.imag, **f64)
+    lam = torch.tensor(0.6, **f64)
+    vc = torch.tensor(V0[cons.numpy()], **f64)
+
+    def J(are, aim, lam, vc):
+        V = torch.zeros(M ** 4, dtype=torch.float64).index_put((cons,), vc).reshape(M, M, M, M)
+        return QEvolve.apply(are, aim, lam, V, spec)
+
+    assert float(J(are, aim, lam, vc).detach()) > 1e-3  # a nontrivial Q
+    assert torch.autograd.gradcheck(J, (are, aim, lam, vc), eps=1e-6, atol=1e-8, rtol=1e-5)
+
+
+def test_autotune_changes_no_bit(tmp_path):
+    """The autotuner only picks a launch schedule: H psi is bitwise unchanged,
+    the pick is one of the candidates and a second basis reads it back from
+    the cache file."""
+    M = 6
+    sectors = [(12, p) for p in range(M)]
+    omega, V = _model("longrange", M, 5)
+    orc, model, b = _pair(M, sectors, omega, 0.2, V)
+    x = torch.from_numpy(W.random_psi(orc.total, 9)).cuda()
+    before = fh.apply_h(model, b, x).cpu().numpy()
+    cache = tmp_path / "tune.txt"
+    cfg, ms = fh.autotune(model, b, x, cache_path=cache)
+    assert ms > 0
+    assert cfg["blocks_per_cu"] in (0, 1, 2, 3) and cfg["xcd_order"] in (0, 1)
+    assert cfg["prefix_modes"] in (0, 2, 3) and cfg["tile_order"] == (1 if cfg["prefix_modes"] else 0)
+    assert np.array_equal(fh.apply_h(model, b, x).cpu().numpy(), before)
+    assert _rel(before, orc.apply_h(x.cpu().numpy())) <= 1e-13
+    b2 = fh.Basis(M, sectors)
+    cfg2, ms2 = fh.autotune(model, b2, x, cache_path=cache)
+    assert cfg2 == cfg and ms2 == pytest.approx(ms, rel=1e-5)
+    assert np.array_equal(fh.apply_h(model, b2, x).cpu().numpy(), before)
