@@ -223,6 +223,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / multi-rhs / adjoint comparisons")
+    ap.add_argument("--forms-only", action="store_true", help="run only the form comparisons (one JSON object)")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--xcd-order", type=int, default=1)
     ap.add_argument("--tile-order", type=int, default=0)
@@ -240,6 +241,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.forms_only:
+        print(json.dumps({"forms": forms()}), flush=True)
+        return
     w = W.large_sector()
     model = fh.Model(w.M, w.omega, w.Lambda, w.V)
     basis = fh.Basis(w.M, w.sectors)
