@@ -97,8 +97,9 @@ def forms():
                   same draws run one at a time (M=10, N=30, all 10 P);
       adjoint   : forward + discrete adjoint (gradients of J) vs the forward
                   alone (M=6 number state N=30, 3000 steps; M=6 coherent
-                  state, mean 20, 331 sectors, 100 steps), with a central
-                  difference of J in Lambda on the first.
+                  state, mean 20, 331 sectors, 100 steps; one M=10 field-number
+                  draw, 212M states, 10 steps), with a central difference of
+                  J in Lambda on the first.
     Equal-accuracy check: the two paths of a pair return the same amplitudes
     (max |difference| is reported; the kernels sum in the same order)."""
     import numpy as np
@@ -184,17 +185,25 @@ def forms():
     # ---- adjoint vs forward
     adj = []
     for w, obj, steps, ck in ((W.adjoint_number(30), fh.FH_J_NMODE, 3000, 100),
-                              (W.adjoint_coherent(20.0), fh.FH_J_Q, 100, 10)):
+                              (W.adjoint_coherent(20.0), fh.FH_J_Q, 100, 10),
+                              (W.fieldnumber_draws(16, 30), fh.FH_J_PO, 10, 5)):
         model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
         log(f"adjoint: {w.name}, {basis.total} states, {steps} steps")
-        init = (lambda b=basis, w=w: fh.init_number(b, w.init_params) if w.init == "number"
-                else fh.init_coherent(b, w.init_params))
+
+        def init(b=basis, w=w):
+            if w.init == "number":
+                return fh.init_number(b, w.init_params)
+            if w.init == "fieldnumber":
+                return fh.init_fieldnumber(b, w.init_params[0])  # one phase draw
+            return fh.init_coherent(b, w.init_params)
+
         psi = init()
         _, tf = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps))
         psi0 = init()
         res, ta = timed(lambda: fh.adjoint_rk4(model, basis, psi0, w.dt, steps, ck, obj, 0))
-        rec = {"workload": w.name, "states": basis.total, "steps": steps, "checkpoint_every": ck,
-               "objective": {fh.FH_J_Q: "Q", fh.FH_J_NMODE: "<n_0>(T)"}[obj],
+        name = w.name + (", draw 0 only" if w.init == "fieldnumber" else "")
+        rec = {"workload": name, "states": basis.total, "steps": steps, "checkpoint_every": ck,
+               "objective": {fh.FH_J_Q: "Q", fh.FH_J_NMODE: "<n_0>(T)", fh.FH_J_PO: "1 - lambda_p/n_tot"}[obj],
                "forward_s": tf, "adjoint_s": ta, "ratio": ta / tf,
                "J": float(res["J"][0]), "dJ_dLambda": float(res["dLambda"][0])}
         if steps == 3000:

@@ -206,8 +206,12 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
  *   FH_J_Q      : Q of Eq. (Qparam)
  *   FH_J_PO     : 1 - lambda_p / n_tot (Eq. POcriterion)
  *   FH_J_NMODE  : <a_k^+ a_k> with k = obj_mode
- * Checkpoints every ckpt_every steps.  work: device scratch of at least
- * fh_adjoint_work_states(...) * total * nrhs fh_c64.  Outputs: lambda0
+ * Checkpoints every ckpt_every steps; inside a segment the states are
+ * recomputed forward.  work: device scratch of at least
+ * fh_adjoint_work_states(...) * total * nrhs fh_c64; with at least
+ * fh_adjoint_work_states_kept(...) states the stage inputs of every step are
+ * kept from that recompute instead of being computed again (three H psi per
+ * step fewer; same result to rounding order).  Outputs: lambda0
  * (device, total*nrhs) = 2 dJ/d conj(psi0); J[nrhs], dJ_dLambda[nrhs],
  * dJ_dV[nrhs*M^4] (host; dJ_dV may be NULL).  Each ordered, momentum-
  * conserving V entry is an independent parameter; entries that do not conserve
@@ -216,7 +220,8 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
 #define FH_J_Q 0
 #define FH_J_PO 1
 #define FH_J_NMODE 2
-int64_t fh_adjoint_work_states(int64_t nsteps, int64_t ckpt_every);
+int64_t fh_adjoint_work_states(int64_t nsteps, int64_t ckpt_every);       /* segments + C + 10 */
+int64_t fh_adjoint_work_states_kept(int64_t nsteps, int64_t ckpt_every);  /* segments + 4 C + 10 */
 fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi0, double dt,
                          int64_t nsteps, int64_t ckpt_every, int objective, int obj_mode, fh_c64* work,
                          int64_t work_states, fh_c64* lambda0, double* J, double* dJ_dLambda,

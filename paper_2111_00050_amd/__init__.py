@@ -72,6 +72,7 @@ SIGNATURES = {
     "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_adjoint_work_states": (_I64, [_I64, _I64]),
+    "fh_adjoint_work_states_kept": (_I64, [_I64, _I64]),
     "fh_adjoint_rk4": (_I, [_P, _P, _I, _P, _D, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
     "fh_coherent_vjp": (_I, [_P, _I, _P, _P, _P, _P, _P]),
 }
@@ -362,11 +363,15 @@ def evolve_rk4(model, basis, psi, dt, nsteps, every=0, flags=0, work=None):
 
 
 # --------------------------------------------------------------- adjoint ---
-def adjoint_rk4(model, basis, psi0, dt, nsteps, ckpt_every, objective=FH_J_Q, mode=0, work=None):
-    """Discrete adjoint of nsteps RK4 steps: J, dJ/dLambda, dJ/dV and lambda0 = 2 dJ/d conj(psi0)."""
+def adjoint_rk4(model, basis, psi0, dt, nsteps, ckpt_every, objective=FH_J_Q, mode=0, work=None,
+                keep_stage_inputs=True):
+    """Discrete adjoint of nsteps RK4 steps: J, dJ/dLambda, dJ/dV and lambda0 = 2 dJ/d conj(psi0).
+    With keep_stage_inputs (and work=None) the work buffer is sized so that the stage inputs of a
+    segment are kept (fh_adjoint_work_states_kept) rather than recomputed."""
     torch = _torch()
     nrhs = _nrhs_of(basis, psi0)
-    need = int(_lib.fh_adjoint_work_states(int(nsteps), int(ckpt_every)))
+    size_fn = _lib.fh_adjoint_work_states_kept if keep_stage_inputs else _lib.fh_adjoint_work_states
+    need = int(size_fn(int(nsteps), int(ckpt_every)))
     if need < 0:
         raise ValueError("nsteps and ckpt_every must be >= 1")
     if work is None:

@@ -1267,6 +1267,12 @@ int64_t fh_adjoint_work_states(int64_t nsteps, int64_t ckpt_every) {
     return nseg + std::min(ckpt_every, nsteps) + 10;
 }
 
+int64_t fh_adjoint_work_states_kept(int64_t nsteps, int64_t ckpt_every) {
+    if (nsteps < 1 || ckpt_every < 1) return -1;
+    const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+    return nseg + 4 * std::min(ckpt_every, nsteps) + 10;
+}
+
 fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi0, double dt, int64_t nsteps,
                          int64_t ckpt_every, int objective, int obj_mode, fh_c64* work, int64_t work_states,
                          fh_c64* lambda0, double* J, double* dJ_dLambda, double* dJ_dV, void* stream) {
@@ -1283,21 +1289,27 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         hipStream_t s = as_stream(stream);
         const int64_t C = std::min(ckpt_every, nsteps);
         const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+        // With room for 4 vectors per step of a segment, the stage inputs of
+        // every step are kept from the segment's forward recompute instead of
+        // being recomputed (3 H psi per step fewer).
+        const bool keep = work_states >= fh_adjoint_work_states_kept(nsteps, ckpt_every);
         const int64_t vec = 2 * b->total * nrhs;  // doubles per state vector
         const size_t vbytes = sizeof(double) * (size_t)vec;
         double* W = reinterpret_cast<double*>(work);
         auto buf = [&](int64_t q) { return W + q * vec; };
-        double* ckpt0 = buf(0);
-        double* seg0 = buf(nseg);
-        double* acc = buf(nseg + C + 0);
-        double* yA = buf(nseg + C + 1);
-        double* yB = buf(nseg + C + 2);
-        double* y2 = buf(nseg + C + 3);
-        double* y3 = buf(nseg + C + 4);
-        double* y4 = buf(nseg + C + 5);
-        double* gacc = buf(nseg + C + 6);
-        double* kbA = buf(nseg + C + 7);
-        double* kbB = buf(nseg + C + 8);
+        // layout: checkpoints [nseg] | segment states [C] | (kept) y2, y3, y4 [C each] | scratch [10]
+        auto segst = [&](int64_t t) { return buf(nseg + t); };
+        auto kept = [&](int which, int64_t t) { return buf(nseg + (int64_t)which * C + t); };  // which = 1..3
+        const int64_t sb = nseg + (keep ? 4 * C : C);
+        double* acc = buf(sb + 0);
+        double* yA = buf(sb + 1);
+        double* yB = buf(sb + 2);
+        double* y2 = buf(sb + 3);
+        double* y3 = buf(sb + 4);
+        double* y4 = buf(sb + 5);
+        double* gacc = buf(sb + 6);
+        double* kbA = buf(sb + 7);
+        double* kbB = buf(sb + 8);
         double* g = reinterpret_cast<double*>(lambda0);
 
         fh_model* mT = nullptr;
@@ -1308,34 +1320,41 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
             ~Del() { fh_model_destroy(p); }
         } del{mT};
 
-        // One forward RK4 step in place on y (4 fused stages).
-        auto step = [&](double* y) -> fh_status {
+        // One forward RK4 step from -> to (4 fused stages; to may equal from),
+        // leaving the stage inputs y2, y3, y4 in the given buffers (the third
+        // may alias the first).  With nstages = 3 only the stage inputs.
+        auto step = [&](const double* from, double* to, double* o2, double* o3, double* o4,
+                        int nstages) -> fh_status {
             StageArgs base = stage_base(m, b);
             base.ks_re = 0.0;
             base.ks_im = -1.0;
             StageArgs s1 = base, s2 = base, s3 = base, s4 = base;
-            s1.x = y; s1.base = y; s1.acc = acc; s1.ynext = yA; s1.mode = kFirst; s1.a = dt / 6; s1.c0 = 1; s1.b = dt / 2;
-            s2.x = yA; s2.base = y; s2.acc = acc; s2.ynext = yB; s2.mode = kMid; s2.a = dt / 3; s2.c0 = 1; s2.b = dt / 2;
-            s3.x = yB; s3.base = y; s3.acc = acc; s3.ynext = yA; s3.mode = kMid; s3.a = dt / 3; s3.c0 = 1; s3.b = dt;
-            s4.x = yA; s4.acc = acc; s4.baseout = y; s4.mode = kLast; s4.a = dt / 6;
-            for (StageArgs* a : {&s1, &s2, &s3, &s4}) {
-                fh_status e = launch_stage(b, nrhs, *a, 0, s, nullptr);
+            s1.x = from; s1.base = from; s1.acc = acc; s1.ynext = o2; s1.mode = kFirst; s1.a = dt / 6; s1.c0 = 1; s1.b = dt / 2;
+            s2.x = o2; s2.base = from; s2.acc = acc; s2.ynext = o3; s2.mode = kMid; s2.a = dt / 3; s2.c0 = 1; s2.b = dt / 2;
+            s3.x = o3; s3.base = from; s3.acc = acc; s3.ynext = o4; s3.mode = kMid; s3.a = dt / 3; s3.c0 = 1; s3.b = dt;
+            s4.x = o4; s4.acc = acc; s4.baseout = to; s4.mode = kLast; s4.a = dt / 6;
+            StageArgs* all[4] = {&s1, &s2, &s3, &s4};
+            for (int q = 0; q < nstages; ++q) {
+                fh_status e = launch_stage(b, nrhs, *all[q], 0, s, nullptr);
                 if (e != FH_OK) return e;
             }
             return FH_OK;
         };
 
-        // ---- forward sweep storing checkpoints
-        FH_HIP(hipMemcpyAsync(ckpt0, psi0, vbytes, hipMemcpyDeviceToDevice, s));
-        FH_HIP(hipMemcpyAsync(seg0, psi0, vbytes, hipMemcpyDeviceToDevice, s));
+        // ---- forward sweep storing checkpoints (the running state is the
+        //      first segment slot)
+        double* run = segst(0);
+        FH_HIP(hipMemcpyAsync(buf(0), psi0, vbytes, hipMemcpyDeviceToDevice, s));
+        FH_HIP(hipMemcpyAsync(run, psi0, vbytes, hipMemcpyDeviceToDevice, s));
         for (int64_t k = 0; k < nseg; ++k) {
             const int64_t len = std::min(C, nsteps - k * C);
             for (int64_t t = 0; t < len; ++t) {
-                st = step(seg0);
+                st = step(run, run, yA, yB, yA, 4);
                 if (st != FH_OK) return st;
             }
-            if (k + 1 < nseg) FH_HIP(hipMemcpyAsync(buf(k + 1), seg0, vbytes, hipMemcpyDeviceToDevice, s));
+            if (k + 1 < nseg) FH_HIP(hipMemcpyAsync(buf(k + 1), run, vbytes, hipMemcpyDeviceToDevice, s));
         }
+        double* seg0 = run;  // psi_T
         // ---- terminal condition (seg0 holds psi_T)
         std::vector<double> rec(FH_MOMENT_DOUBLES(M));
         std::vector<double> cf;
@@ -1364,47 +1383,47 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         b2.x = kbB; b2.mode = kMid; b2.a = 1; b2.c0 = dt / 6; b2.b = dt / 2; b2.ynext = kbA;
         b1.x = kbA; b1.mode = kLast; b1.a = 1; b1.baseout = g;
 
-        StageArgs fb = stage_base(m, b);
-        fb.ks_re = 0.0;
-        fb.ks_im = -1.0;
-        fb.acc = acc;
 
         for (int64_t k = nseg - 1; k >= 0; --k) {
             const int64_t len = std::min(C, nsteps - k * C);
-            FH_HIP(hipMemcpyAsync(seg0, buf(k), vbytes, hipMemcpyDeviceToDevice, s));
+            // state of step t of the segment: the checkpoint itself for t = 0
+            auto state = [&](int64_t t) { return t == 0 ? buf(k) : segst(t); };
             for (int64_t t = 1; t < len; ++t) {
-                FH_HIP(hipMemcpyAsync(seg0 + t * vec, seg0 + (t - 1) * vec, vbytes, hipMemcpyDeviceToDevice, s));
-                st = step(seg0 + t * vec);
+                st = keep ? step(state(t - 1), state(t), kept(1, t - 1), kept(2, t - 1), kept(3, t - 1), 4)
+                          : step(state(t - 1), state(t), yA, yB, yA, 4);
+                if (st != FH_OK) return st;
+            }
+            if (keep) {
+                st = step(state(len - 1), nullptr, kept(1, len - 1), kept(2, len - 1), kept(3, len - 1), 3);
                 if (st != FH_OK) return st;
             }
             for (int64_t t = len - 1; t >= 0; --t) {
-                double* ps = seg0 + t * vec;
+                double* ps = state(t);
                 // stage inputs y2, y3, y4 of this step
-                StageArgs f1 = fb, f2 = fb, f3 = fb;
-                f1.x = ps; f1.base = ps; f1.mode = kFirst; f1.a = dt / 6; f1.c0 = 1; f1.b = dt / 2; f1.ynext = y2;
-                f2.x = y2; f2.base = ps; f2.mode = kMid; f2.a = dt / 3; f2.c0 = 1; f2.b = dt / 2; f2.ynext = y3;
-                f3.x = y3; f3.base = ps; f3.mode = kMid; f3.a = dt / 3; f3.c0 = 1; f3.b = dt; f3.ynext = y4;
-                for (StageArgs* a : {&f1, &f2, &f3}) {
-                    st = launch_stage(b, nrhs, *a, 0, s, nullptr);
+                double* s2p = keep ? kept(1, t) : y2;
+                double* s3p = keep ? kept(2, t) : y3;
+                double* s4p = keep ? kept(3, t) : y4;
+                if (!keep) {
+                    st = step(ps, nullptr, y2, y3, y4, 3);
                     if (st != FH_OK) return st;
                 }
                 // reverse stages (transposed model) and parameter correlators
                 st = launch_stage(b, nrhs, b4, 0, s, nullptr);
                 if (st != FH_OK) return st;
                 for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, g, dt / 6, y4, gtot + q * gt_per, s);
+                    st = run_corr(b, nrhs, q, g, dt / 6, s4p, gtot + q * gt_per, s);
                     if (st != FH_OK) return st;
                 }
                 st = launch_stage(b, nrhs, b3, 0, s, nullptr);
                 if (st != FH_OK) return st;
                 for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, kbA, 1.0, y3, gtot + q * gt_per, s);
+                    st = run_corr(b, nrhs, q, kbA, 1.0, s3p, gtot + q * gt_per, s);
                     if (st != FH_OK) return st;
                 }
                 st = launch_stage(b, nrhs, b2, 0, s, nullptr);
                 if (st != FH_OK) return st;
                 for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, kbB, 1.0, y2, gtot + q * gt_per, s);
+                    st = run_corr(b, nrhs, q, kbB, 1.0, s2p, gtot + q * gt_per, s);
                     if (st != FH_OK) return st;
                     st = run_corr(b, nrhs, q, kbA, 1.0, ps, gtot + q * gt_per, s);
                     if (st != FH_OK) return st;

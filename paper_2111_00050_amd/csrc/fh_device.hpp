@@ -142,6 +142,10 @@ __device__ __forceinline__ int move_rank(const int* sT, const int (&key)[M], con
 
 typedef double v2d __attribute__((ext_vector_type(2)));
 
+// Fourth word of a raw buffer resource on gfx9-family GPUs (32-bit data
+// format; no swizzle, no stride); out-of-range loads return zero.
+constexpr int kBufferWord3 = 0x00020000;
+
 __device__ __forceinline__ v2d nt_load(const double* p) {
     return __builtin_nontemporal_load(reinterpret_cast<const v2d*>(p));
 }
@@ -225,6 +229,7 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
         SecInfo sc;
         sc.N = __builtin_amdgcn_readfirstlane(secs[tsec].N);
         sc.P = __builtin_amdgcn_readfirstlane(secs[tsec].P);
+        sc.dim = __builtin_amdgcn_readfirstlane(secs[tsec].dim);
         {
             const unsigned long long o = (unsigned long long)secs[tsec].off;
             const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)o);
@@ -268,10 +273,18 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
             // combinations: all neighbour ranks first, then every gather of the
             // chunk in flight together, then the FMAs.  For each row pair the
             // source terms W c_kl x are summed first and scaled by c_ij once.
-            // Lanes whose row pair cannot be annihilated (c_ij == 0) gather
-            // their own row and scale it by zero, so the chunk is straight-line
-            // code.  Every NRHS sums each column in the same order.
-            const char* xb = reinterpret_cast<const char*>(xs);
+            // Lanes whose row pair cannot be annihilated (c_ij == 0) load zero
+            // (one rhs) or their own row (several) and scale it by zero, so the
+            // chunk is straight-line code.  Every NRHS sums each column in the
+            // same order.
+            // One right-hand side: gathers are buffer loads over the sector's
+            // bytes.  A lane whose row pair is empty (c_ij == 0) asks for byte
+            // kNoGather, past the end of every sector (fewer than 2^28 states),
+            // and the load returns zero without a memory access; the term is
+            // scaled by c_ij == 0 in any case.
+            constexpr unsigned kNoGather = 0xFFFFFF00u;
+            const __amdgpu_buffer_rsrc_t xrs = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)xs, (short)0, (int)((unsigned)sc.dim * 16u), kBufferWord3);  // bytes, < 2^32
             static_for<0, M>([&](auto Cc) {
                 constexpr int c = decltype(Cc)::value;
                 constexpr int S = CB::class_size(c);
@@ -315,15 +328,15 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
                                 constexpr int s = decltype(Sx)::value;
                                 r -= (unsigned)sT[key[s] + move_offset<M>(s, k, l, i, j)];
                             });
-                            const unsigned src = cij[r1] != 0.0 ? r : rowS;
+                            const unsigned src = cij[r1] != 0.0 ? r : (NRHS == 1 ? kNoGather : rowS);
                             if constexpr (NRHS == 1) off[decltype(Q)::value] = src;
                             else off[decltype(Q)::value] = (long long)src * NRHS + sub;
                         });
                         double2 v[NQC][NR];
                         static_for<0, NQC>([&](auto Q) {
                             if constexpr (NRHS == 1) {
-                                v[decltype(Q)::value][0] =
-                                    *reinterpret_cast<const double2*>(xb + off[decltype(Q)::value]);
+                                v[decltype(Q)::value][0] = __builtin_bit_cast(
+                                    double2, __builtin_amdgcn_raw_buffer_load_b128(xrs, off[decltype(Q)::value], 0, 0));
                             } else {
                                 const double2* sp = xs + off[decltype(Q)::value];
 #pragma unroll

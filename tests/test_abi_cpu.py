@@ -64,6 +64,9 @@ def test_host_validation_paths():
     assert lib.fh_basis_create(M, M, 0, fh._np_ptr(N), fh._np_ptr(P), ctypes.byref(h)) == fh.FH_EINVAL
     assert lib.fh_adjoint_work_states(0, 10) == -1
     assert lib.fh_adjoint_work_states(3000, 100) == 30 + 100 + 10
+    assert lib.fh_adjoint_work_states_kept(3000, 100) == 30 + 400 + 10
+    assert lib.fh_adjoint_work_states_kept(7, 100) == 1 + 28 + 10
+    assert lib.fh_adjoint_work_states_kept(5, 0) == -1
 
 
 def test_derive_host_only_against_oracle():

@@ -304,6 +304,10 @@ def test_adjoint_vs_oracle():
         ref = evolve.adjoint(orc, psi0o, dt, nsteps, mk(orc))
         psi0 = fh.init_coherent(b, alpha)
         res = fh.adjoint_rk4(model, b, psi0, dt, nsteps, 7, obj, mode=1)
+        # recomputing the stage inputs instead of keeping them changes no bit
+        res2 = fh.adjoint_rk4(model, b, psi0, dt, nsteps, 7, obj, mode=1, keep_stage_inputs=False)
+        assert np.array_equal(res["lambda0"].cpu().numpy(), res2["lambda0"].cpu().numpy())
+        assert res["dLambda"][0] == res2["dLambda"][0] and np.array_equal(res["dV"], res2["dV"])
         assert abs(res["J"][0] - ref["J"]) <= 1e-10
         assert abs(res["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
         # only momentum-conserving entries are parameters of the model; the
@@ -365,3 +369,22 @@ def test_autotune_changes_no_bit(tmp_path):
     cfg2, ms2 = fh.autotune(model, b2, x, cache_path=cache)
     assert cfg2 == cfg and ms2 == pytest.approx(ms, rel=1e-5)
     assert np.array_equal(fh.apply_h(model, b2, x).cpu().numpy(), before)
+
+
+def test_adjoint_two_rhs_matches_single():
+    """Two coherent states adjointed together give, column by column, what
+    each gives alone (the multi-rhs stage kernel sums each column in the
+    single-rhs order)."""
+    M, Lam, dt, nsteps = 4, 0.3, 5e-3, 12
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    b = fh.Basis(M, W.all_sectors(M, 8))
+    model = fh.Model(M, omega, Lam, V)
+    al = np.stack([W.coherent_amplitudes(s, M, 1.3) for s in (61, 62)])
+    both = fh.adjoint_rk4(model, b, fh.init_coherent(b, al), dt, nsteps, 5, fh.FH_J_Q)
+    lam_both = both["lambda0"].cpu().numpy()
+    for q in range(2):
+        one = fh.adjoint_rk4(model, b, fh.init_coherent(b, al[q]), dt, nsteps, 5, fh.FH_J_Q)
+        assert abs(both["J"][q] - one["J"][0]) <= 1e-14
+        assert abs(both["dLambda"][q] - one["dLambda"][0]) <= 1e-12 * max(1.0, abs(one["dLambda"][0]))
+        assert np.abs(both["dV"][q] - one["dV"][0]).max() <= 1e-12 * max(1.0, np.abs(one["dV"][0]).max())
+        assert _rel(lam_both[:, q], one["lambda0"].cpu().numpy()) <= 1e-13
