@@ -520,6 +520,7 @@ fh_status run_moments(const fh_basis* b, int nrhs, int rhs, const double* psi, d
     a.Nmax = b->Nmax;
     a.partial = b->d_partial;
     a.xcd_order = b->xcd_order;
+    a.occ = b->d_occ;
     std::vector<double> v((size_t)groups * 2 * NO, 0.0);
     if (nt > 0) {
         const int G = persistent_grid(b, b->ks->moments_fn, lds, nt);

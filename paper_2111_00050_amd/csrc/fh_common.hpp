@@ -162,6 +162,7 @@ struct MomArgs {
     int Nmax;
     double* partial;    // [group][grid][kMomOut] complex
     int xcd_order;
+    const unsigned char* occ;  // occupation records
 };
 constexpr int momentsOut(int M) { return 2 * M + 1; }
 // LDS layout of the table-staging kernels: rank table (ints, padded to an even

@@ -187,6 +187,23 @@ __device__ __forceinline__ void stage_tables(const int* T, int Tn, const double*
 }
 
 
+// Occupations of a state from its record (occ_stride(M) bytes).
+template <int M>
+__device__ __forceinline__ void load_occ(const unsigned char* occ, long long state, int (&n)[M]) {
+    if constexpr (M <= 8) {
+        const uint2 w = reinterpret_cast<const uint2*>(occ)[state];
+#pragma unroll
+        for (int m = 0; m < M; ++m) n[m] = (int)(((m < 4 ? w.x : w.y) >> (8 * (m & 3))) & 0xffu);
+    } else {
+        const uint4 w = reinterpret_cast<const uint4*>(occ)[state];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            const unsigned v = m < 4 ? w.x : m < 8 ? w.y : m < 12 ? w.z : w.w;
+            n[m] = (int)((v >> (8 * (m & 3))) & 0xffu);
+        }
+    }
+}
+
 // ------------------------------------------------------------ H psi stage --
 template <int M, int NRHS>
 __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(StageArgs A) {
@@ -416,10 +433,13 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
 // ---------------------------------------------------------------- moments --
 // group 0: [0] <psi|psi>, [1+i] <a_i>, [1+M+i] <a_i^+ a_i>
 // group 1+i: [j] <a_i^+ a_j> (j != i), [M+l] <a_i a_l> (l >= i)
-// Each term: sum_n conj(psi(n')) c psi(n) with n' the image of n.
+// Each term: sum_n conj(psi(n')) c psi(n) with n' the image of n.  Rows start
+// from their occupation records; tile, sector and sector-map entries are
+// uniform per workgroup and read with scalar loads.
 template <int M>
 __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
     constexpr int NO = momentsOut(M);
+    using C4 = const __attribute__((address_space(4))) int;
     extern __shared__ int smem[];
     int* sT = smem;
     double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
@@ -427,6 +447,10 @@ __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
     stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
 
     const double2* __restrict__ X = reinterpret_cast<const double2*>(A.psi);
+    const __attribute__((address_space(4))) Tile* tiles = (const __attribute__((address_space(4))) Tile*)A.tiles;
+    const __attribute__((address_space(4))) SecInfo* secs =
+        (const __attribute__((address_space(4))) SecInfo*)A.secs;
+    C4* secmap = (C4*)A.secmap;
     const int g = blockIdx.y;
     const int nrhs = A.nrhs, rhs = A.rhs;
     double acc[2 * NO];
@@ -438,32 +462,43 @@ __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
         acc[2 * slot] = fma(c, y.x * x.x + y.y * x.y, acc[2 * slot]);
         acc[2 * slot + 1] = fma(c, y.x * x.y - y.y * x.x, acc[2 * slot + 1]);
     };
+    // partner sector (N2, P2): its dimension and offset, false if absent
+    auto partner = [&](int N2, int P2, int& dim, long long& off) -> bool {
+        const int sid = __builtin_amdgcn_readfirstlane(secmap[N2 * M + P2]);
+        if (sid < 0) return false;
+        dim = __builtin_amdgcn_readfirstlane(secs[sid].dim);
+        const unsigned long long o = (unsigned long long)secs[sid].off;
+        off = (long long)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(o >> 32)) << 32) |
+                          __builtin_amdgcn_readfirstlane((unsigned)o));
+        return true;
+    };
 
     const int vb = virtual_block(A.xcd_order);
     for (int t = vb; t < A.ntiles; t += gridDim.x) {
-        const Tile tl = A.tiles[t];
-        if ((int)threadIdx.x >= tl.nrows) continue;
-        const SecInfo sc = A.secs[tl.sec];
-        const int row = tl.row0 + (int)threadIdx.x;
+        const int tsec = __builtin_amdgcn_readfirstlane(tiles[t].sec);
+        const int row0 = __builtin_amdgcn_readfirstlane(tiles[t].row0);
+        const int nrows = __builtin_amdgcn_readfirstlane(tiles[t].nrows);
+        const int N = __builtin_amdgcn_readfirstlane(secs[tsec].N);
+        const int P = __builtin_amdgcn_readfirstlane(secs[tsec].P);
+        const long long soff = secs[tsec].off;
+        if ((int)threadIdx.x >= nrows) continue;
+        const int row = row0 + (int)threadIdx.x;
         int n[M];
-        unrank_row<M>(sT, A.Rdim, sc.N, sc.P, row, n);
+        load_occ<M>(A.occ, soff + row, n);
         int key[M], C[M];
         row_keys<M>(sT, A.Rdim, n, key, C);
-        const double2 x = X[(sc.off + row) * nrhs + rhs];
-        const int N = sc.N, P = sc.P;
+        const double2 x = X[(soff + row) * nrhs + rhs];
         if (g == 0) {
             const double x2 = x.x * x.x + x.y * x.y;
             acc[0] += x2;
             static_for<0, M>([&](auto I) {
                 constexpr int i = decltype(I)::value;
                 acc[2 * (1 + M + i)] = fma((double)n[i], x2, acc[2 * (1 + M + i)]);
-                if (N >= 1 && n[i] >= 1) {
-                    const int sid = A.secmap[(N - 1) * M + modM<M>(P - i)];
-                    if (sid >= 0) {
-                        const SecInfo pd = A.secs[sid];
-                        const int r = move_rank<M, 0, i, -1, -1, i, -1>(sT, key, C, pd.dim);
-                        add(1 + i, X[(pd.off + r) * nrhs + rhs], sSq[n[i]], x);
-                    }
+                int pdim;
+                long long poff;
+                if (N >= 1 && partner(N - 1, modM<M>(P - i), pdim, poff) && n[i] >= 1) {
+                    const int r = move_rank<M, 0, i, -1, -1, i, -1>(sT, key, C, pdim);
+                    add(1 + i, X[(poff + r) * nrhs + rhs], sSq[n[i]], x);
                 }
             });
         } else {
@@ -474,14 +509,12 @@ __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
                     static_for<0, M>([&](auto J) {
                         constexpr int j = decltype(J)::value;
                         if constexpr (j != i) {
-                            if (n[j] >= 1) {
-                                const int sid = A.secmap[N * M + modM<M>(P + i - j)];
-                                if (sid >= 0) {
-                                    const SecInfo pd = A.secs[sid];
-                                    constexpr int hi = i > j ? i : j;
-                                    const int r = move_rank<M, 0, hi, i, -1, j, -1>(sT, key, C, pd.dim);
-                                    add(j, X[(pd.off + r) * nrhs + rhs], sSq[n[j]] * sSq[n[i] + 1], x);
-                                }
+                            int pdim;
+                            long long poff;
+                            if (partner(N, modM<M>(P + i - j), pdim, poff) && n[j] >= 1) {
+                                constexpr int hi = i > j ? i : j;
+                                const int r = move_rank<M, 0, hi, i, -1, j, -1>(sT, key, C, pdim);
+                                add(j, X[(poff + r) * nrhs + rhs], sSq[n[j]] * sSq[n[i] + 1], x);
                             }
                         }
                     });
@@ -489,14 +522,12 @@ __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
                     static_for<i, M>([&](auto L) {
                         constexpr int l = decltype(L)::value;
                         const bool ok = (l == i) ? (n[i] >= 2) : (n[i] >= 1 && n[l] >= 1);
-                        if (N >= 2 && ok) {
-                            const int sid = A.secmap[(N - 2) * M + modM<M>(P - i - l)];
-                            if (sid >= 0) {
-                                const SecInfo pd = A.secs[sid];
-                                const int r = move_rank<M, 0, l, -1, -1, i, l>(sT, key, C, pd.dim);
-                                const double c = (l == i) ? sSq[n[i]] * sSq[n[i] - 1] : sSq[n[l]] * sSq[n[i]];
-                                add(M + l, X[(pd.off + r) * nrhs + rhs], c, x);
-                            }
+                        int pdim;
+                        long long poff;
+                        if (N >= 2 && partner(N - 2, modM<M>(P - i - l), pdim, poff) && ok) {
+                            const int r = move_rank<M, 0, l, -1, -1, i, l>(sT, key, C, pdim);
+                            const double c = (l == i) ? sSq[n[i]] * sSq[n[i] - 1] : sSq[n[l]] * sSq[n[i]];
+                            add(M + l, X[(poff + r) * nrhs + rhs], c, x);
                         }
                     });
                 }
@@ -587,23 +618,6 @@ __global__ __launch_bounds__(kTileRows) void onebody_kernel(OneBodyArgs A) {
 }
 
 // ------------------------------------------------------- correlators -----
-// Occupations of a state from its record (occ_stride(M) bytes).
-template <int M>
-__device__ __forceinline__ void load_occ(const unsigned char* occ, long long state, int (&n)[M]) {
-    if constexpr (M <= 8) {
-        const uint2 w = reinterpret_cast<const uint2*>(occ)[state];
-#pragma unroll
-        for (int m = 0; m < M; ++m) n[m] = (int)(((m < 4 ? w.x : w.y) >> (8 * (m & 3))) & 0xffu);
-    } else {
-        const uint4 w = reinterpret_cast<const uint4*>(occ)[state];
-#pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const unsigned v = m < 4 ? w.x : m < 8 ? w.y : m < 12 ? w.z : w.w;
-            n[m] = (int)((v >> (8 * (m & 3))) & 0xffu);
-        }
-    }
-}
-
 // Fill the occupation records of every state (unrank once per state).
 template <int M>
 __global__ __launch_bounds__(kTileRows) void occ_table_kernel(OccArgs A) {
