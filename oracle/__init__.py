@@ -16,6 +16,7 @@ Modules:
   oracle.evolve       classical RK4 and the discrete adjoint of the RK4 map
   oracle.derived      Q, Penrose-Onsager eigenvalue, squeezing V_-
   oracle.dense        dense-matrix references for sectors of <= ~500 states
+  oracle.classical    mean-field (classical field) equations and their RK4
 
 Parity pins: see tests/test_oracle_pins.py.
 """

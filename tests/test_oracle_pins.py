@@ -16,6 +16,8 @@ identity, a dense-matrix propagator, a printed number of the paper).
   P9  coherent state at t = 0 (Q = 0, lambda_p = n_tot, V_- = 1, normal order)
   P10 the paper's long-range coherent test problem, n_tot |chi| (Sec. IV.E)
   P11 field-number and number eigenstates (Sec. II.B, Sec. IV.C/D remarks)
+  C1-C4 classical field equations: free phases, single-mode and site-wise
+      Kerr rotations, invariants of the flow
 """
 import itertools
 import math
@@ -372,3 +374,59 @@ def test_p12_adjoint_dense_expm_and_zeros(oracle_lib):
     h = 1e-5
     fd = (J_exact(w.Lambda + h) - J_exact(w.Lambda - h)) / (2 * h)
     assert abs(res["dLambda"] - fd) < 1e-6 * max(1, abs(fd))
+
+
+# ----------------------------------------------------- classical field (C) --
+# The mean-field equations of Sec. II / Sec. III.A (oracle.classical), pinned
+# to closed forms of the classical dynamics.
+from oracle import classical  # noqa: E402
+
+
+def _rk4_factor(z):
+    return 1 + z + z * z / 2 + z ** 3 / 6 + z ** 4 / 24
+
+
+def test_c1_classical_free_phases():
+    """Lambda = 0: each amplitude is multiplied by R(-i w dt) per step."""
+    M, dt, n = 6, 0.07, 40
+    om = W.omega_quadratic(M)
+    a0 = np.stack([W.coherent_amplitudes(s, M, 3.0) for s in (1, 2)])
+    aT, _ = classical.rk4(om, 0.0, W.V_longrange(M), a0, dt, n)
+    np.testing.assert_allclose(aT, a0 * _rk4_factor(-1j * om * dt) ** n, rtol=1e-13, atol=0)
+
+
+def test_c2_classical_single_mode_kerr():
+    """M = 1: d alpha/dt = -i (w + Lambda v |alpha|^2) alpha, a pure rotation."""
+    w, v, Lam, a0, dt, n = 0.5, 0.8, 0.35, 1.1 - 0.7j, 1e-3, 3000
+    V = np.full((1, 1, 1, 1), v)
+    aT, traj = classical.rk4(np.array([w]), Lam, V, np.array([a0]), dt, n, every=500)
+    for s, a in enumerate(traj):
+        t = s * 500 * dt
+        assert abs(a[0] - a0 * np.exp(-1j * (w + Lam * v * abs(a0) ** 2) * t)) <= 1e-10
+
+
+def test_c3_classical_contact_sitewise_kerr():
+    """Contact V, w = 0: with b = F alpha (F_xk = e^{2 pi i k x / M}/sqrt(M)),
+    each b_x rotates at rate Lambda M |b_x|^2 (the classical image of P5)."""
+    M, Lam, dt, n = 5, 0.3, 1e-3, 2000
+    F = np.exp(2j * np.pi * np.outer(np.arange(M), np.arange(M)) / M) / np.sqrt(M)
+    a0 = W.coherent_amplitudes(9, M, 2.0)
+    aT, _ = classical.rk4(np.zeros(M), Lam, W.V_contact(M), a0, dt, n)
+    b0 = F @ a0
+    bT = b0 * np.exp(-1j * Lam * M * np.abs(b0) ** 2 * n * dt)
+    np.testing.assert_allclose(F @ aT, bT, rtol=0, atol=1e-10)
+
+
+def test_c4_classical_invariants():
+    """Hermitian V: sum |alpha|^2 and the mean-field energy are invariants of the
+    flow (conserved to the RK4 error); a non-Hermitian V breaks the first."""
+    M, Lam, dt, n = 5, 0.6, 2e-4, 2000
+    om = np.random.default_rng(4).uniform(0, 2, M)
+    V = W.V_random_symmetric(M, 7)
+    a0 = W.coherent_amplitudes(11, M, 2.0)
+    aT, _ = classical.rk4(om, Lam, V, a0, dt, n)
+    assert abs(np.sum(np.abs(aT) ** 2) - np.sum(np.abs(a0) ** 2)) <= 1e-11
+    assert abs(classical.energy(om, Lam, V, aT) - classical.energy(om, Lam, V, a0)) <= 1e-10
+    Vn = W.V_random(M, 7)
+    aN, _ = classical.rk4(om, Lam, Vn, a0, dt, n)
+    assert abs(np.sum(np.abs(aN) ** 2) - np.sum(np.abs(a0) ** 2)) > 1e-6
