@@ -200,6 +200,22 @@ fh_status fh_basis_set_tile_order(fh_basis* b, int order, int prefix_modes);
 fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c64* x, fh_c64* out,
                             const char* cache_path, int* chosen, double* best_ms, void* stream);
 
+/* --------------------------------------------------------- classical field --
+ * Mean-field trajectories of the same model (Sec. II, Eq. clEqnMotion;
+ * Sec. III.A, Eq. classicalFieldEqns): every operator of the Heisenberg
+ * equation of a_p replaced by its mean,
+ *   d alpha_p/dt = -i [ omega_p alpha_p
+ *                       + (Lambda/2) sum_{jkl} (V_pjkl + V_jpkl) conj(alpha_j) alpha_k alpha_l ],
+ * integrated with classical RK4 (step dt, nsteps steps) in one launch, one
+ * GPU thread per trajectory.  alpha: device [ntraj*M] fh_c64 (trajectory-
+ * major): initial values on entry (Sec. III.A uses sqrt(n_p) for a number
+ * eigenstate and z_p for coherent and field-number states), values at
+ * t = nsteps*dt on return.  out: device [(nsteps/every + 1)*ntraj*M] fh_c64
+ * receiving the values at steps 0, every, 2 every, ... (every >= 1), or NULL.
+ * Asynchronous on the stream. */
+fh_status fh_classical_rk4(const fh_model* m, int ntraj, fh_c64* alpha, double dt, int64_t nsteps, int64_t every,
+                           fh_c64* out, void* stream);
+
 /* ---------------------------------------------------------------- adjoint --
  * Discrete adjoint of nsteps RK4 steps from psi0 (device), for the objective
  * J at t = nsteps*dt:

@@ -71,6 +71,7 @@ SIGNATURES = {
     "fh_moments": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
+    "fh_classical_rk4": (_I, [_P, _I, _P, _D, _I64, _I64, _P, _P]),
     "fh_adjoint_work_states": (_I64, [_I64, _I64]),
     "fh_adjoint_work_states_kept": (_I64, [_I64, _I64]),
     "fh_adjoint_rk4": (_I, [_P, _P, _I, _P, _D, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
@@ -363,6 +364,23 @@ def evolve_rk4(model, basis, psi, dt, nsteps, every=0, flags=0, work=None):
 
 
 # --------------------------------------------------------------- adjoint ---
+def classical_rk4(model, alpha0, dt, nsteps, every=0):
+    """Mean-field trajectories (fh_classical_rk4): alpha0 is [ntraj, M] or [M]
+    complex (numpy or a CUDA complex128 tensor).  Returns (alpha_T, outputs) with
+    alpha_T a [ntraj, M] tensor and outputs a [nout, ntraj, M] tensor of the
+    values at steps 0, every, ... (None when every == 0)."""
+    torch = _torch()
+    a = torch.as_tensor(alpha0, dtype=torch.complex128, device="cuda").reshape(-1, model.M).clone()
+    ntraj = a.shape[0]
+    out = None
+    if every > 0:
+        out = torch.empty((nsteps // every + 1, ntraj, model.M), dtype=torch.complex128, device="cuda")
+    _check(_lib.fh_classical_rk4(model.handle, ntraj, _dev_ptr(a, torch.complex128, "alpha"), float(dt), int(nsteps),
+                                 int(every), None if out is None else _dev_ptr(out, torch.complex128, "out"),
+                                 _stream()))
+    return a, out
+
+
 def adjoint_rk4(model, basis, psi0, dt, nsteps, ckpt_every, objective=FH_J_Q, mode=0, work=None,
                 keep_stage_inputs=True):
     """Discrete adjoint of nsteps RK4 steps: J, dJ/dLambda, dJ/dV and lambda0 = 2 dJ/d conj(psi0).

@@ -128,6 +128,14 @@ void build_coef(fh_model* m) {
     for (int p1 = 0; p1 < NP; ++p1)
         for (int p2 = 0; p2 < NP; ++p2)
             if (p1 != p2 && cls(p1) == cls(p2)) m->coef.push_back(pairsum(p1, p2));
+    // classical field: U[p][j][k] = (Lambda/2)(V_pjkl + V_jpkl), l = p + j - k mod M
+    m->ucoef_off = m->coef.size();
+    for (int p = 0; p < M; ++p)
+        for (int j = 0; j < M; ++j)
+            for (int k = 0; k < M; ++k) {
+                const int l = posmod(p + j - k, M);
+                m->coef.push_back(0.5 * m->Lambda * (Vat(p, j, k, l) + Vat(j, p, k, l)));
+            }
 }
 
 fh_status model_upload(fh_model* m) {
@@ -868,6 +876,30 @@ fh_status fh_apply_h(const fh_model* m, const fh_basis* b, int nrhs, const fh_c6
         a.out = reinterpret_cast<double*>(out);
         a.mode = kApply;
         return launch_stage(b, nrhs, a, 0, as_stream(stream), nullptr);
+    });
+}
+
+fh_status fh_classical_rk4(const fh_model* m, int ntraj, fh_c64* alpha, double dt, int64_t nsteps, int64_t every,
+                           fh_c64* out, void* stream) {
+    return Guard::run([&]() -> fh_status {
+        FH_REQUIRE(m != nullptr, FH_EINVAL, "fh_classical_rk4: model is NULL");
+        FH_REQUIRE(ntraj >= 0 && nsteps >= 0, FH_EINVAL, "fh_classical_rk4: ntraj and nsteps must be >= 0");
+        FH_REQUIRE(std::isfinite(dt), FH_EINVAL, "fh_classical_rk4: dt not finite");
+        FH_REQUIRE(out == nullptr || every >= 1, FH_EINVAL, "fh_classical_rk4: every must be >= 1 with out");
+        if (ntraj == 0) return FH_OK;
+        FH_REQUIRE(alpha != nullptr, FH_EINVAL, "fh_classical_rk4: alpha is NULL");
+        ClassicalArgs a{};
+        a.alpha = reinterpret_cast<double*>(alpha);
+        a.out = reinterpret_cast<double*>(out);
+        a.omega = m->d_coef;
+        a.U = m->d_coef + m->ucoef_off;
+        a.dt = dt;
+        a.nsteps = nsteps;
+        a.every = out ? every : 1;
+        a.ntraj = ntraj;
+        kernel_set(m->M)->classical(a, as_stream(stream));
+        FH_HIP(hipGetLastError());
+        return FH_OK;
     });
 }
 

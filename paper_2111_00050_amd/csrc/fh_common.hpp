@@ -220,6 +220,17 @@ struct CorrArgs {
 };
 constexpr int kCorrOutMax = 36;  // (max class size)^2 for M <= 10
 
+// Classical (mean-field) trajectories, one per thread.
+struct ClassicalArgs {
+    double* alpha;        // [ntraj][M] complex, in/out
+    double* out;          // [nout][ntraj][M] complex, or nullptr
+    const double* omega;  // [M]
+    const double* U;      // [M][M][M]: U[p][j][k] = (Lambda/2)(V_pjkl + V_jpkl), l = p + j - k mod M
+    double dt;
+    long long nsteps, every;
+    int ntraj;
+};
+
 // Initial states.
 struct InitArgs {
     double* psi;

@@ -840,6 +840,92 @@ __global__ __launch_bounds__(kTileRows) void vjp_kernel(VjpArgs A) {
     if (threadIdx.x < NV) A.partial[(size_t)blockIdx.x * 2 * (kMaxM + 1) + threadIdx.x] = outv[threadIdx.x];
 }
 
+// ------------------------------------------------------- classical field --
+// Mean-field equations of the model (Sec. II, Eq. clEqnMotion; Sec. III.A,
+// Eq. classicalFieldEqns): the Heisenberg equation of a_p with operators
+// replaced by their means,
+//   d alpha_p/dt = -i [ w_p alpha_p + sum_{j,k} U[p][j][k] conj(alpha_j) alpha_k alpha_l ],
+//   l = p + j - k (mod M),  U[p][j][k] = (Lambda/2)(V_pjkl + V_jpkl)
+// (only momentum-conserving V entries exist).  One thread per trajectory,
+// every RK4 step of the run in one launch; coefficients are scalar loads.
+template <int M>
+__device__ __forceinline__ void classical_rhs(const __attribute__((address_space(4))) double* w,
+                                              const __attribute__((address_space(4))) double* U,
+                                              const double2 (&y)[M], double2 (&f)[M]) {
+    static_for<0, M>([&](auto Pp) {
+        constexpr int p = decltype(Pp)::value;
+        double sr = 0.0, si = 0.0;
+        static_for<0, M>([&](auto Jj) {
+            constexpr int j = decltype(Jj)::value;
+            double rr = 0.0, ri = 0.0;  // sum_k U y_k y_l
+            static_for<0, M>([&](auto Kk) {
+                constexpr int k0 = decltype(Kk)::value;
+                constexpr int l0 = cmod<M>(p + j - k0);
+                constexpr int k = k0 < l0 ? k0 : l0, l = k0 < l0 ? l0 : k0;  // one product per pair
+                const double u = U[(p * M + j) * M + k0];
+                const double pr = y[k].x * y[l].x - y[k].y * y[l].y;
+                const double pi = y[k].x * y[l].y + y[k].y * y[l].x;
+                rr = fma(u, pr, rr);
+                ri = fma(u, pi, ri);
+            });
+            sr = fma(y[j].x, rr, fma(y[j].y, ri, sr));   // Re conj(y_j) R
+            si = fma(y[j].x, ri, fma(-y[j].y, rr, si));  // Im conj(y_j) R
+        });
+        const double xr = fma(w[p], y[p].x, sr), xi = fma(w[p], y[p].y, si);
+        f[p] = make_double2(xi, -xr);  // -i (xr + i xi)
+    });
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void classical_kernel(ClassicalArgs A) {
+    const int tr = blockIdx.x * blockDim.x + threadIdx.x;
+    if (tr >= A.ntraj) return;
+    using CD = const __attribute__((address_space(4))) double;
+    CD* w = (CD*)A.omega;
+    CD* U = (CD*)A.U;
+    double2* alpha = reinterpret_cast<double2*>(A.alpha);
+    double2* out = reinterpret_cast<double2*>(A.out);
+    const double dt = A.dt, h2 = 0.5 * A.dt, h6 = A.dt / 6.0;
+    double2 y[M];
+#pragma unroll
+    for (int p = 0; p < M; ++p) y[p] = alpha[(long long)tr * M + p];
+    for (long long s = 0;; ++s) {
+        if (out && s % A.every == 0) {
+            const long long o = ((s / A.every) * A.ntraj + tr) * M;
+#pragma unroll
+            for (int p = 0; p < M; ++p) out[o + p] = y[p];
+        }
+        if (s == A.nsteps) break;
+        double2 k[M], acc[M], t[M];
+        classical_rhs<M>(w, U, y, k);  // k1
+#pragma unroll
+        for (int p = 0; p < M; ++p) {
+            acc[p] = k[p];
+            t[p] = make_double2(fma(h2, k[p].x, y[p].x), fma(h2, k[p].y, y[p].y));
+        }
+        classical_rhs<M>(w, U, t, k);  // k2
+#pragma unroll
+        for (int p = 0; p < M; ++p) {
+            acc[p] = make_double2(fma(2.0, k[p].x, acc[p].x), fma(2.0, k[p].y, acc[p].y));
+            t[p] = make_double2(fma(h2, k[p].x, y[p].x), fma(h2, k[p].y, y[p].y));
+        }
+        classical_rhs<M>(w, U, t, k);  // k3
+#pragma unroll
+        for (int p = 0; p < M; ++p) {
+            acc[p] = make_double2(fma(2.0, k[p].x, acc[p].x), fma(2.0, k[p].y, acc[p].y));
+            t[p] = make_double2(fma(dt, k[p].x, y[p].x), fma(dt, k[p].y, y[p].y));
+        }
+        classical_rhs<M>(w, U, t, k);  // k4
+#pragma unroll
+        for (int p = 0; p < M; ++p) {
+            y[p].x = fma(h6, acc[p].x + k[p].x, y[p].x);
+            y[p].y = fma(h6, acc[p].y + k[p].y, y[p].y);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < M; ++p) alpha[(long long)tr * M + p] = y[p];
+}
+
 // ------------------------------------------------------ rank / unrank -----
 template <int M>
 __global__ void rank_kernel(RankArgs A) {

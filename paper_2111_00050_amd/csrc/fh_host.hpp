@@ -15,7 +15,8 @@ struct fh_model {
     std::vector<double> omega;   // [M]
     std::vector<double> V;       // [M^4]
     double Lambda = 0.0;
-    std::vector<double> coef;    // omega[M] | Wd[NP] | W[NC]
+    std::vector<double> coef;    // omega[M] | Wd[NP] | W[NC] | U[M^3] (classical field)
+    size_t ucoef_off = 0;        // offset of U in coef
     double* d_coef = nullptr;
     int device = 0;
 };

@@ -36,6 +36,7 @@ struct KernelSet {
     const void* corr_fn;
     void (*corr)(const CorrArgs&, int grid, int classes, size_t lds, hipStream_t);
     void (*occ_table)(const OccArgs&, int grid, size_t lds, hipStream_t);
+    void (*classical)(const ClassicalArgs&, hipStream_t);
     void (*init_product)(const InitArgs&, int grid, size_t lds, hipStream_t);
     void (*vjp)(const VjpArgs&, int grid, size_t lds, hipStream_t);
     void (*rank)(const RankArgs&, hipStream_t);

@@ -25,6 +25,10 @@ void onebody_l(const OneBodyArgs& a, int grid, size_t lds, hipStream_t s) {
 void corr_l(const CorrArgs& a, int grid, int classes, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((corr_kernel<kM>), dim3(grid, classes), dim3(kTileRows), lds, s, a);
 }
+void classical_l(const ClassicalArgs& a, hipStream_t s) {
+    const int nb = (a.ntraj + 255) / 256;
+    if (nb > 0) hipLaunchKernelGGL((classical_kernel<kM>), dim3(nb), dim3(256), 0, s, a);
+}
 void occ_l(const OccArgs& a, int grid, size_t lds, hipStream_t s) {
     hipLaunchKernelGGL((occ_table_kernel<kM>), dim3(grid), dim3(kTileRows), lds, s, a);
 }
@@ -64,6 +68,7 @@ const KernelSet* FH_CAT(kernel_set_M, FH_INST_M)() {
         reinterpret_cast<const void*>(&corr_kernel<kM>),
         &corr_l,
         &occ_l,
+        &classical_l,
         &init_l,
         &vjp_l,
         &rank_l,
