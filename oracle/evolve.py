@@ -47,6 +47,23 @@ def rk4(orc, psi0, dt, nsteps, every=0, observe=None):
     return psi, out
 
 
+def taylor2(orc, psi0, dt, nsteps, c2=0.5, every=0, observe=None):
+    """The paper's second-order step, Eq. (Q_int):
+        psi <- psi - i dt H psi - c2 dt^2 H (H psi),
+    with c2 = 1/2 for a Taylor step of exp(-i H dt) (the printed equation has
+    c2 = 1).  Outputs as in rk4()."""
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    out = []
+    for s in range(nsteps + 1):
+        if every > 0 and s % every == 0 and observe is not None:
+            out.append(observe(s, s * dt, psi))
+        if s == nsteps:
+            break
+        h1 = orc.apply_h(psi)
+        psi = psi - 1j * dt * h1 - c2 * dt * dt * orc.apply_h(h1)
+    return psi, out
+
+
 def _stages(orc, psi, dt):
     f = lambda y: -1j * orc.apply_h(y)
     y1 = psi

@@ -18,6 +18,8 @@ identity, a dense-matrix propagator, a printed number of the paper).
   P11 field-number and number eigenstates (Sec. II.B, Sec. IV.C/D remarks)
   C1-C4 classical field equations: free phases, single-mode and site-wise
       Kerr rotations, invariants of the flow
+  T1-T2 the paper's second-order step (Eq. Q_int): free factor 1 + z + c2 z^2,
+      dense propagator, second order only with c2 = 1/2
 """
 import itertools
 import math
@@ -430,3 +432,37 @@ def test_c4_classical_invariants():
     Vn = W.V_random(M, 7)
     aN, _ = classical.rk4(om, Lam, Vn, a0, dt, n)
     assert abs(np.sum(np.abs(aN) ** 2) - np.sum(np.abs(a0) ** 2)) > 1e-6
+
+
+# ----------------------------------------------- second-order step (T) ------
+@pytest.mark.parametrize("c2", [0.5, 1.0])
+def test_t1_taylor2_free_factor(oracle_lib, c2):
+    """Lambda = 0: each amplitude is multiplied by 1 + z + c2 z^2, z = -i E dt."""
+    M, dt, n = 4, 0.02, 30
+    sectors = [(5, p) for p in range(M)]
+    o = Oracle(M, M, W.omega_quadratic(M), 0.0, W.V_contact(M), sectors)
+    psi0 = W.random_psi(o.total, 3)
+    E = o.all_occupations() @ W.omega_quadratic(M)
+    psi, _ = evolve.taylor2(o, psi0, dt, n, c2=c2)
+    z = -1j * E * dt
+    np.testing.assert_allclose(psi, psi0 * (1 + z + c2 * z * z) ** n, rtol=1e-13, atol=0)
+
+
+def test_t2_taylor2_dense_propagator(oracle_lib):
+    """Interacting sector: the step equals the dense matrix (I - i dt H - dt^2 H^2 / 2)
+    applied n times; the printed c2 = 1 gives a different, first-order step."""
+    w = W.tiny_number()
+    o = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    psi0 = states.number_state(o, w.init_params)
+    H = dense.dense_h(o)
+    n = 100
+    Pm = np.eye(H.shape[0]) - 1j * w.dt * H - 0.5 * w.dt ** 2 * (H @ H)
+    want = np.linalg.matrix_power(Pm, n) @ psi0
+    psi, _ = evolve.taylor2(o, psi0, w.dt, n)
+    np.testing.assert_allclose(psi, want, rtol=0, atol=1e-12)
+    # second order: error against exp(-i H t) about t (E dt)^2 E / 6; c2 = 1 is first order
+    T = n * w.dt
+    exact = dense.expm_evolve(H, psi0, T)
+    err_half = np.linalg.norm(psi - exact)
+    psi1, _ = evolve.taylor2(o, psi0, w.dt, n, c2=1.0)
+    assert err_half < 0.1 * np.linalg.norm(psi1 - exact)
