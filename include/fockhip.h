@@ -45,6 +45,11 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+/* The library is built with hidden visibility; exactly the entry points
+ * declared here are exported. */
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
 
 typedef enum {
     FH_OK = 0,
@@ -174,6 +179,16 @@ fh_status fh_evolve_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* 
                         double dt, int64_t nsteps, int64_t obs_every, double* moments,
                         int64_t moments_capacity, int flags, fh_timing* timing, void* stream);
 
+/* The paper's second-order step, Eq. (Q_int), in place on psi:
+ *   psi <- psi - i dt H psi - c2 dt^2 H (H psi)
+ * c2 = 1/2 makes it the second-order Taylor step of exp(-i H dt); the printed
+ * equation has c2 = 1 (first order).  Two fused H psi launches per step.
+ * work: device scratch of 2*total*nrhs fh_c64.  Moments, flags and timing as
+ * for fh_evolve_rk4. */
+fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work, double dt,
+                            double c2, int64_t nsteps, int64_t obs_every, double* moments, int64_t moments_capacity,
+                            int flags, fh_timing* timing, void* stream);
+
 /* Launch configuration of the stage kernel for this basis: persistent
  * workgroups per compute unit (0 = occupancy limit) and the XCD-aware tile
  * order (0 = plain round robin, 1 = contiguous tile ranges per XCD).
@@ -248,6 +263,9 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
 fh_status fh_coherent_vjp(const fh_basis* b, int nrhs, const fh_c64* alpha, const fh_c64* lambda0,
                           double* d_re, double* d_im, void* stream);
 
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
+#endif
 #ifdef __cplusplus
 }
 #endif

@@ -71,6 +71,7 @@ SIGNATURES = {
     "fh_moments": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
+    "fh_evolve_taylor2": (_I, [_P, _P, _I, _P, _P, _D, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_classical_rk4": (_I, [_P, _I, _P, _D, _I64, _I64, _P, _P]),
     "fh_adjoint_work_states": (_I64, [_I64, _I64]),
     "fh_adjoint_work_states_kept": (_I64, [_I64, _I64]),
@@ -363,7 +364,26 @@ def evolve_rk4(model, basis, psi, dt, nsteps, every=0, flags=0, work=None):
     return EvolveResult(rec[:nrec], steps, tm.stage_ms, tm.stage_launches, tm.wall_ms)
 
 
-# --------------------------------------------------------------- adjoint ---
+def evolve_taylor2(model, basis, psi, dt, nsteps, c2=0.5, every=0, flags=0, work=None):
+    """The paper's second-order step (Eq. Q_int) in place on psi: psi <- psi - i dt H psi -
+    c2 dt^2 H H psi (c2 = 1/2: Taylor step; the printed equation has c2 = 1)."""
+    torch = _torch()
+    nrhs = _nrhs_of(basis, psi)
+    if work is None:
+        work = torch.empty((2 * basis.total * nrhs,), dtype=torch.complex128, device=psi.device)
+    M = basis.M
+    nrec = nsteps // every + 1 if every > 0 else 0
+    rec = np.zeros((max(nrec, 1), nrhs, moment_doubles(M)))
+    tm = fh_timing()
+    _check(_lib.fh_evolve_taylor2(model.handle, basis.handle, nrhs, _dev_ptr(psi, torch.complex128, "psi"),
+                                  _dev_ptr(work, torch.complex128, "work"), float(dt), float(c2), int(nsteps),
+                                  int(every), _np_ptr(rec), rec.size if nrec else 0, int(flags), ctypes.byref(tm),
+                                  _stream()))
+    steps = np.arange(nrec) * every if nrec else np.zeros(0, int)
+    return EvolveResult(rec[:nrec], steps, tm.stage_ms, tm.stage_launches, tm.wall_ms)
+
+
+# ------------------------------------------------------- classical field ---
 def classical_rk4(model, alpha0, dt, nsteps, every=0):
     """Mean-field trajectories (fh_classical_rk4): alpha0 is [ntraj, M] or [M]
     complex (numpy or a CUDA complex128 tensor).  Returns (alpha_T, outputs) with
@@ -381,6 +401,7 @@ def classical_rk4(model, alpha0, dt, nsteps, every=0):
     return a, out
 
 
+# --------------------------------------------------------------- adjoint ---
 def adjoint_rk4(model, basis, psi0, dt, nsteps, ckpt_every, objective=FH_J_Q, mode=0, work=None,
                 keep_stage_inputs=True):
     """Discrete adjoint of nsteps RK4 steps: J, dJ/dLambda, dJ/dV and lambda0 = 2 dJ/d conj(psi0).

@@ -34,6 +34,8 @@ COMMON = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
+    # export only the C ABI (include/fockhip.h marks its declarations visible)
+    "-fvisibility=hidden",
 ]
 
 

@@ -1023,36 +1023,129 @@ fh_status fh_moments(const fh_basis* b, int nrhs, int rhs, const fh_c64* psi, do
     });
 }
 
+}  // extern "C"
+
+namespace {
+
+// Shared driver of the explicit steppers: one step is the given sequence of
+// fused stage launches (buffers already bound); moments every obs_every steps;
+// optionally the step is captured once into a HIP graph and replayed.
+fh_status evolve_driver(const fh_basis* b, int nrhs, double* P, std::vector<StageArgs>& stages, int64_t nsteps,
+                        int64_t obs_every, double* moments, int64_t moments_capacity, int flags, fh_timing* timing,
+                        hipStream_t s, std::chrono::steady_clock::time_point t0, const char* who) {
+    const int M = b->M;
+    const int64_t nrec = obs_every > 0 ? nsteps / obs_every + 1 : 0;
+    const int64_t per = (int64_t)FH_MOMENT_DOUBLES(M) * nrhs;
+    if (nrec > 0) {
+        FH_REQUIRE(moments != nullptr, FH_EINVAL, std::string(who) + ": moments buffer is NULL");
+        FH_REQUIRE(moments_capacity >= nrec * per, FH_ENOMEM, std::string(who) + ": moments buffer too small");
+    }
+    StageTimer tm;
+    fh_status st = tm.init((flags & FH_TIMING) != 0, s);
+    if (st != FH_OK) return st;
+    StageTimer* tmp = (flags & FH_TIMING) ? &tm : nullptr;
+
+    auto record = [&](int64_t r) -> fh_status {
+        for (int q = 0; q < nrhs; ++q) {
+            fh_status e = run_moments(b, nrhs, q, P, moments + r * per + (int64_t)q * FH_MOMENT_DOUBLES(M), s, M + 1);
+            if (e != FH_OK) return e;
+        }
+        return FH_OK;
+    };
+    auto step_direct = [&]() -> fh_status {
+        for (StageArgs& a : stages) {
+            fh_status e = launch_stage(b, nrhs, a, flags, s, tmp);
+            if (e != FH_OK) return e;
+        }
+        return FH_OK;
+    };
+
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (flags & FH_GRAPH) {
+        FH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        fh_status e = step_direct();
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (e != FH_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return e;
+        }
+        if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return hip_fail(ie, "hipGraphInstantiate");
+        }
+    }
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    };
+
+    int64_t r = 0;
+    if (nrec > 0) {
+        st = record(r++);
+        if (st != FH_OK) { cleanup(); return st; }
+    }
+    for (int64_t step = 1; step <= nsteps; ++step) {
+        if (exec) {
+            hipError_t e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipGraphLaunch"); }
+        } else {
+            st = step_direct();
+            if (st != FH_OK) { cleanup(); return st; }
+        }
+        if (obs_every > 0 && step % obs_every == 0) {
+            st = record(r++);
+            if (st != FH_OK) { cleanup(); return st; }
+        }
+    }
+    cleanup();
+    st = tm.flush();
+    if (st != FH_OK) return st;
+    FH_HIP(hipStreamSynchronize(s));
+    if (timing) {
+        timing->stage_ms = tm.ms;
+        timing->stage_launches = tm.launches;
+        timing->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    for (int64_t q = 0; q < nrec * per; q += FH_MOMENT_DOUBLES(M))
+        if (!std::isfinite(moments[q])) {
+            set_error(std::string(who) + ": non-finite norm (unstable dt?)");
+            return FH_ESTATE;
+        }
+    return FH_OK;
+}
+
+fh_status check_evolve_args(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi, const fh_c64* work,
+                            double dt, int64_t nsteps, int64_t obs_every, int flags, void* stream, const char* who) {
+    if (!check_model_basis(m, b)) return FH_EINVAL;
+    const std::string w(who);
+    FH_REQUIRE(!bad_nrhs(nrhs), FH_EINVAL, "nrhs must be 1, 2, 4, 8 or 16");
+    FH_REQUIRE(psi != nullptr && work != nullptr, FH_EINVAL, w + ": NULL buffer");
+    FH_REQUIRE(nsteps >= 0 && obs_every >= 0, FH_EINVAL, w + ": negative step count");
+    FH_REQUIRE(std::isfinite(dt), FH_EINVAL, w + ": dt not finite");
+    FH_REQUIRE(!((flags & FH_GRAPH) && (flags & FH_TIMING)), FH_EINVAL, "FH_GRAPH and FH_TIMING are exclusive");
+    FH_REQUIRE(!((flags & FH_GRAPH) && stream == nullptr), FH_EINVAL, "FH_GRAPH needs a non-default stream");
+    return FH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 fh_status fh_evolve_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work, double dt,
                         int64_t nsteps, int64_t obs_every, double* moments, int64_t moments_capacity, int flags,
                         fh_timing* timing, void* stream) {
     return Guard::run([&]() -> fh_status {
         const auto t0 = std::chrono::steady_clock::now();
-        if (!check_model_basis(m, b)) return FH_EINVAL;
-        FH_REQUIRE(!bad_nrhs(nrhs), FH_EINVAL, "nrhs must be 1, 2, 4, 8 or 16");
-        FH_REQUIRE(psi != nullptr && work != nullptr, FH_EINVAL, "fh_evolve_rk4: NULL buffer");
-        FH_REQUIRE(nsteps >= 0 && obs_every >= 0, FH_EINVAL, "fh_evolve_rk4: negative step count");
-        FH_REQUIRE(std::isfinite(dt), FH_EINVAL, "fh_evolve_rk4: dt not finite");
-        FH_REQUIRE(!((flags & FH_GRAPH) && (flags & FH_TIMING)), FH_EINVAL, "FH_GRAPH and FH_TIMING are exclusive");
-        FH_REQUIRE(!((flags & FH_GRAPH) && stream == nullptr), FH_EINVAL, "FH_GRAPH needs a non-default stream");
-        const int M = b->M;
-        const int64_t nrec = obs_every > 0 ? nsteps / obs_every + 1 : 0;
-        const int64_t per = (int64_t)FH_MOMENT_DOUBLES(M) * nrhs;
-        if (nrec > 0) {
-            FH_REQUIRE(moments != nullptr, FH_EINVAL, "fh_evolve_rk4: moments buffer is NULL");
-            FH_REQUIRE(moments_capacity >= nrec * per, FH_ENOMEM, "fh_evolve_rk4: moments buffer too small");
-        }
-        hipStream_t s = as_stream(stream);
+        fh_status st = check_evolve_args(m, b, nrhs, psi, work, dt, nsteps, obs_every, flags, stream, "fh_evolve_rk4");
+        if (st != FH_OK) return st;
         double* P = reinterpret_cast<double*>(psi);
         const int64_t vec = 2 * b->total * nrhs;
         double* acc = reinterpret_cast<double*>(work);
         double* yA = acc + vec;
         double* yB = yA + vec;
-        StageTimer tm;
-        fh_status st = tm.init((flags & FH_TIMING) != 0, s);
-        if (st != FH_OK) return st;
-        StageTimer* tmp = (flags & FH_TIMING) ? &tm : nullptr;
-
         StageArgs base = stage_base(m, b);
         base.ks_re = 0.0;
         base.ks_im = -1.0;
@@ -1061,79 +1154,35 @@ fh_status fh_evolve_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* 
         s2.x = yA; s2.base = P; s2.acc = acc; s2.ynext = yB; s2.mode = kMid; s2.a = dt / 3; s2.c0 = 1; s2.b = dt / 2;
         s3.x = yB; s3.base = P; s3.acc = acc; s3.ynext = yA; s3.mode = kMid; s3.a = dt / 3; s3.c0 = 1; s3.b = dt;
         s4.x = yA; s4.acc = acc; s4.baseout = P; s4.mode = kLast; s4.a = dt / 6;
+        std::vector<StageArgs> stages = {s1, s2, s3, s4};
+        return evolve_driver(b, nrhs, P, stages, nsteps, obs_every, moments, moments_capacity, flags, timing,
+                             as_stream(stream), t0, "fh_evolve_rk4");
+    });
+}
 
-        auto record = [&](int64_t r) -> fh_status {
-            for (int q = 0; q < nrhs; ++q) {
-                fh_status e = run_moments(b, nrhs, q, P, moments + r * per + (int64_t)q * FH_MOMENT_DOUBLES(M), s,
-                                          M + 1);
-                if (e != FH_OK) return e;
-            }
-            return FH_OK;
-        };
-        auto step_direct = [&]() -> fh_status {
-            for (StageArgs* a : {&s1, &s2, &s3, &s4}) {
-                fh_status e = launch_stage(b, nrhs, *a, flags, s, tmp);
-                if (e != FH_OK) return e;
-            }
-            return FH_OK;
-        };
-
-        hipGraphExec_t exec = nullptr;
-        hipGraph_t graph = nullptr;
-        if (flags & FH_GRAPH) {
-            FH_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-            fh_status e = step_direct();
-            hipError_t ce = hipStreamEndCapture(s, &graph);
-            if (e != FH_OK) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return e;
-            }
-            if (ce != hipSuccess) return hip_fail(ce, "hipStreamEndCapture");
-            hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-            if (ie != hipSuccess) {
-                (void)hipGraphDestroy(graph);
-                return hip_fail(ie, "hipGraphInstantiate");
-            }
-        }
-        auto cleanup = [&]() {
-            if (exec) (void)hipGraphExecDestroy(exec);
-            if (graph) (void)hipGraphDestroy(graph);
-        };
-
-        int64_t r = 0;
-        if (nrec > 0) {
-            st = record(r++);
-            if (st != FH_OK) { cleanup(); return st; }
-        }
-        for (int64_t step = 1; step <= nsteps; ++step) {
-            if (exec) {
-                hipError_t e = hipGraphLaunch(exec, s);
-                if (e != hipSuccess) { cleanup(); return hip_fail(e, "hipGraphLaunch"); }
-            } else {
-                st = step_direct();
-                if (st != FH_OK) { cleanup(); return st; }
-            }
-            if (obs_every > 0 && step % obs_every == 0) {
-                st = record(r++);
-                if (st != FH_OK) { cleanup(); return st; }
-            }
-        }
-        cleanup();
-        st = tm.flush();
+fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work, double dt,
+                            double c2, int64_t nsteps, int64_t obs_every, double* moments, int64_t moments_capacity,
+                            int flags, fh_timing* timing, void* stream) {
+    return Guard::run([&]() -> fh_status {
+        const auto t0 = std::chrono::steady_clock::now();
+        fh_status st =
+            check_evolve_args(m, b, nrhs, psi, work, dt, nsteps, obs_every, flags, stream, "fh_evolve_taylor2");
         if (st != FH_OK) return st;
-        FH_HIP(hipStreamSynchronize(s));
-        if (timing) {
-            timing->stage_ms = tm.ms;
-            timing->stage_launches = tm.launches;
-            timing->wall_ms =
-                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-        }
-        for (int64_t q = 0; q < nrec * per; q += FH_MOMENT_DOUBLES(M))
-            if (!std::isfinite(moments[q])) {
-                set_error("fh_evolve_rk4: non-finite norm (unstable dt?)");
-                return FH_ESTATE;
-            }
-        return FH_OK;
+        FH_REQUIRE(std::isfinite(c2), FH_EINVAL, "fh_evolve_taylor2: c2 not finite");
+        double* P = reinterpret_cast<double*>(psi);
+        const int64_t vec = 2 * b->total * nrhs;
+        double* acc = reinterpret_cast<double*>(work);
+        double* y = acc + vec;
+        // stage A: k = -i dt H psi;        acc = psi + k,  y = k
+        // stage B: k = -i c2 dt H y;       psi = acc + k = psi - i dt H psi - c2 dt^2 H^2 psi
+        StageArgs sa = stage_base(m, b), sb = sa;
+        sa.x = P; sa.base = P; sa.acc = acc; sa.ynext = y; sa.mode = kFirst;
+        sa.ks_re = 0.0; sa.ks_im = -dt; sa.a = 1.0; sa.c0 = 0.0; sa.b = 1.0;
+        sb.x = y; sb.acc = acc; sb.baseout = P; sb.mode = kLast;
+        sb.ks_re = 0.0; sb.ks_im = -c2 * dt; sb.a = 1.0;
+        std::vector<StageArgs> stages = {sa, sb};
+        return evolve_driver(b, nrhs, P, stages, nsteps, obs_every, moments, moments_capacity, flags, timing,
+                             as_stream(stream), t0, "fh_evolve_taylor2");
     });
 }
 

@@ -222,6 +222,25 @@ def test_rk4_coherent_multisector(flags):
         assert res.stage_launches == 4 * 150 and res.stage_ms > 0
 
 
+@pytest.mark.parametrize("c2,flags", [(0.5, 0), (1.0, 0), (0.5, fh.FH_GRAPH), (0.5, fh.FH_PER_SECTOR)])
+def test_taylor2_vs_oracle(c2, flags):
+    """The paper's second-order step (Eq. Q_int) on the GPU against the oracle's."""
+    M, Lam, dt, nsteps, every = 4, 0.3, 1e-3, 120, 40
+    alpha = W.coherent_amplitudes(17, M, 2.0)
+    sectors = W.all_sectors(M, 12)
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    psi = fh.init_coherent(b, alpha)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        res = fh.evolve_taylor2(model, b, psi, dt, nsteps, c2=c2, every=every, flags=flags)
+    stream.synchronize()
+    ref, recs = evolve.taylor2(orc, states.coherent_state(orc, alpha), dt, nsteps, c2=c2, every=every,
+                               observe=lambda s, t, p: orc.moments(p))
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-10
+    _check_records(M, res, recs)
+
+
 def test_batched_equals_per_sector_bitwise():
     M = 5
     alpha = W.coherent_amplitudes(2, M, 3.0)
