@@ -95,7 +95,8 @@ def forms():
                   (M=6 coherent state, mean 40 bosons, 541 sectors);
       multi_rhs : 16 field-number phase draws as one 16-column vector vs the
                   same draws run one at a time (M=10, N=30, all 10 P);
-      adjoint   : forward + discrete adjoint (gradients of J) vs the forward
+      adjoint   : forward + discrete adjoint (gradients of J), and the
+                  forward-mode tangent in Lambda, vs the forward
                   alone (M=6 number state N=30, 3000 steps; M=6 coherent
                   state, mean 20, 331 sectors, 100 steps; one M=10 field-number
                   draw, 212M states, 10 steps), with a central difference of
@@ -202,10 +203,13 @@ def forms():
         psi0 = init()
         res, ta = timed(lambda: fh.adjoint_rk4(model, basis, psi0, w.dt, steps, ck, obj, 0))
         name = w.name + (", draw 0 only" if w.init == "fieldnumber" else "")
+        tan, tt = timed(lambda: fh.tangent_rk4(model, basis, psi0, w.dt, steps, obj, 0))
+        del tan["psi"], tan["dpsi"]
         rec = {"workload": name, "states": basis.total, "steps": steps, "checkpoint_every": ck,
                "objective": {fh.FH_J_Q: "Q", fh.FH_J_NMODE: "<n_0>(T)", fh.FH_J_PO: "1 - lambda_p/n_tot"}[obj],
                "forward_s": tf, "adjoint_s": ta, "ratio": ta / tf,
-               "J": float(res["J"][0]), "dJ_dLambda": float(res["dLambda"][0])}
+               "J": float(res["J"][0]), "dJ_dLambda": float(res["dLambda"][0]),
+               "tangent_s": tt, "tangent_ratio": tt / tf, "tangent_dJ_dLambda": float(tan["dLambda"][0])}
         if steps == 3000:
             h = 1e-6
             Jpm = []
@@ -215,7 +219,7 @@ def forms():
                 mh.close()
             fd = (Jpm[0] - Jpm[1]) / (2 * h)
             rec["dJ_dLambda_central_difference"] = fd
-        log(f"  ratio {ta / tf:.2f}")
+        log(f"  adjoint ratio {ta / tf:.2f}, tangent ratio {tt / tf:.2f}")
         adj.append(rec)
         del psi, psi0, res
         model.close()

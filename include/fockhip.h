@@ -251,6 +251,18 @@ fh_status fh_classical_rk4(const fh_model* m, int ntraj, fh_c64* alpha, double d
 #define FH_J_Q 0
 #define FH_J_PO 1
 #define FH_J_NMODE 2
+/* Forward-mode tangent of the RK4 map with respect to Lambda: evolves psi
+ * and dpsi = d psi/d Lambda together for nsteps steps (in place; dpsi is
+ * usually zero at the start),
+ *   d psi/dt = -i H psi,   d dpsi/dt = -i H dpsi - i G psi,   G = dH/dLambda
+ * (the interaction term of Eq. Ham with Lambda = 1), differentiated step by
+ * step like the discrete RK4 map, and returns J(psi_T) and
+ * dJ/dLambda = Re <2 dJ/d conj(psi_T), dpsi_T> for the objectives above.
+ * Needs no checkpoints: work is 8*total*nrhs fh_c64 (device); three H psi
+ * per stage.  A memory-light cross-check of fh_adjoint_rk4's dJ/dLambda. */
+fh_status fh_tangent_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* dpsi, fh_c64* work,
+                         double dt, int64_t nsteps, int objective, int obj_mode, double* J, double* dJ_dLambda,
+                         void* stream);
 int64_t fh_adjoint_work_states(int64_t nsteps, int64_t ckpt_every);       /* segments + C + 10 */
 int64_t fh_adjoint_work_states_kept(int64_t nsteps, int64_t ckpt_every);  /* segments + 4 C + 10 */
 fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const fh_c64* psi0, double dt,

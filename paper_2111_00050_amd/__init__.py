@@ -73,6 +73,7 @@ SIGNATURES = {
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_evolve_taylor2": (_I, [_P, _P, _I, _P, _P, _D, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_classical_rk4": (_I, [_P, _I, _P, _D, _I64, _I64, _P, _P]),
+    "fh_tangent_rk4": (_I, [_P, _P, _I, _P, _P, _P, _D, _I64, _I, _I, _P, _P, _P]),
     "fh_adjoint_work_states": (_I64, [_I64, _I64]),
     "fh_adjoint_work_states_kept": (_I64, [_I64, _I64]),
     "fh_adjoint_rk4": (_I, [_P, _P, _I, _P, _D, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
@@ -426,6 +427,23 @@ def adjoint_rk4(model, basis, psi0, dt, nsteps, ckpt_every, objective=FH_J_Q, mo
                                _dev_ptr(lam0, torch.complex128, "lambda0"), _np_ptr(J), _np_ptr(dL), _np_ptr(dV),
                                _stream()))
     return {"J": J, "dLambda": dL, "dV": dV, "lambda0": lam0}
+
+
+def tangent_rk4(model, basis, psi0, dt, nsteps, objective=FH_J_Q, mode=0, dpsi0=None, work=None):
+    """Forward-mode tangent d psi/d Lambda along nsteps RK4 steps (fh_tangent_rk4).
+    psi0 is not modified.  Returns {"J", "dLambda", "psi", "dpsi"}."""
+    torch = _torch()
+    nrhs = _nrhs_of(basis, psi0)
+    psi = psi0.clone()
+    dpsi = torch.zeros_like(psi0) if dpsi0 is None else dpsi0.clone()
+    if work is None:
+        work = torch.empty((8 * basis.total * nrhs,), dtype=torch.complex128, device=psi0.device)
+    J = np.zeros(nrhs)
+    dL = np.zeros(nrhs)
+    _check(_lib.fh_tangent_rk4(model.handle, basis.handle, nrhs, _dev_ptr(psi, torch.complex128, "psi"),
+                               _dev_ptr(dpsi, torch.complex128, "dpsi"), _dev_ptr(work, torch.complex128, "work"),
+                               float(dt), int(nsteps), int(objective), int(mode), _np_ptr(J), _np_ptr(dL), _stream()))
+    return {"J": J, "dLambda": dL, "psi": psi, "dpsi": dpsi}
 
 
 def coherent_vjp(basis, alpha, lambda0):

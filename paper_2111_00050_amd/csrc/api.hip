@@ -1543,6 +1543,96 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
     });
 }
 
+fh_status fh_tangent_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* dpsi, fh_c64* work,
+                         double dt, int64_t nsteps, int objective, int obj_mode, double* J, double* dJ_dLambda,
+                         void* stream) {
+    return Guard::run([&]() -> fh_status {
+        if (!check_model_basis(m, b)) return FH_EINVAL;
+        FH_REQUIRE(!bad_nrhs(nrhs), FH_EINVAL, "nrhs must be 1, 2, 4, 8 or 16");
+        FH_REQUIRE(psi && dpsi && work && J && dJ_dLambda, FH_EINVAL, "fh_tangent_rk4: NULL argument");
+        FH_REQUIRE(nsteps >= 0, FH_EINVAL, "fh_tangent_rk4: negative step count");
+        FH_REQUIRE(std::isfinite(dt), FH_EINVAL, "fh_tangent_rk4: dt not finite");
+        FH_REQUIRE(objective >= FH_J_Q && objective <= FH_J_NMODE, FH_EINVAL, "fh_tangent_rk4: unknown objective");
+        const int M = b->M;
+        hipStream_t s = as_stream(stream);
+        const int64_t vec = 2 * b->total * nrhs;
+        const long long ncplx = (long long)b->total * nrhs;
+        double* P = reinterpret_cast<double*>(psi);
+        double* Z = reinterpret_cast<double*>(dpsi);
+        double* W = reinterpret_cast<double*>(work);
+        double* acc = W;
+        double* yA = W + vec;
+        double* yB = W + 2 * vec;
+        double* zacc = W + 3 * vec;
+        double* zA = W + 4 * vec;
+        double* zB = W + 5 * vec;
+        double* hz = W + 6 * vec;
+        double* gy = W + 7 * vec;
+        // G = dH/dLambda: the interaction alone (omega = 0, Lambda = 1)
+        fh_model* G = nullptr;
+        {
+            std::vector<double> zero(M, 0.0);
+            fh_status st = make_model(M, m->pmod, zero.data(), 1.0, m->V.data(), &G);
+            if (st != FH_OK) return st;
+        }
+        struct Del {
+            fh_model* p;
+            ~Del() { fh_model_destroy(p); }
+        } del{G};
+        StageArgs hb = stage_base(m, b), gb = stage_base(G, b);
+        hb.mode = kApply;
+        gb.mode = kApply;
+        StageArgs base = stage_base(m, b);
+        base.ks_re = 0.0;
+        base.ks_im = -1.0;
+        StageArgs s1 = base, s2 = base, s3 = base, s4 = base;
+        s1.x = P; s1.base = P; s1.acc = acc; s1.ynext = yA; s1.mode = kFirst; s1.a = dt / 6; s1.c0 = 1; s1.b = dt / 2;
+        s2.x = yA; s2.base = P; s2.acc = acc; s2.ynext = yB; s2.mode = kMid; s2.a = dt / 3; s2.c0 = 1; s2.b = dt / 2;
+        s3.x = yB; s3.base = P; s3.acc = acc; s3.ynext = yA; s3.mode = kMid; s3.a = dt / 3; s3.c0 = 1; s3.b = dt;
+        s4.x = yA; s4.acc = acc; s4.baseout = P; s4.mode = kLast; s4.a = dt / 6;
+        // stage inputs of z: z, zA, zB, zA (as y: psi, yA, yB, yA)
+        struct Zs {
+            const double* zin;
+            double* znext;
+            int mode;
+            double a, b;
+        } zs[4] = {{Z, zA, kFirst, dt / 6, dt / 2}, {zA, zB, kMid, dt / 3, dt / 2}, {zB, zA, kMid, dt / 3, dt},
+                   {zA, nullptr, kLast, dt / 6, 0.0}};
+        StageArgs* ps[4] = {&s1, &s2, &s3, &s4};
+        for (int64_t step = 0; step < nsteps; ++step) {
+            for (int q = 0; q < 4; ++q) {
+                StageArgs ga = gb, ha = hb;
+                ga.x = ps[q]->x;  // y_s, before the psi stage overwrites any buffer
+                ga.out = gy;
+                ha.x = zs[q].zin;
+                ha.out = hz;
+                fh_status st = launch_stage(b, nrhs, ga, 0, s, nullptr);
+                if (st != FH_OK) return st;
+                if ((st = launch_stage(b, nrhs, ha, 0, s, nullptr)) != FH_OK) return st;
+                if ((st = launch_stage(b, nrhs, *ps[q], 0, s, nullptr)) != FH_OK) return st;
+                launch_tangent_stage(hz, gy, Z, zacc, zs[q].znext, Z, ncplx, zs[q].mode, zs[q].a, 1.0, zs[q].b, s);
+                FH_HIP(hipGetLastError());
+            }
+        }
+        // dJ/dLambda = Re <g, z(T)> with g = 2 dJ/d conj(psi) at T (same terminal vector as the adjoint)
+        std::vector<double> rec(FH_MOMENT_DOUBLES(M));
+        std::vector<double> cf;
+        double* g = gy;
+        for (int q = 0; q < nrhs; ++q) {
+            fh_status st = run_moments(b, nrhs, q, P, rec.data(), s, M + 1);
+            if (st != FH_OK) return st;
+            if ((st = terminal_coefficients(M, rec.data(), objective, obj_mode, &J[q], cf)) != FH_OK) return st;
+            if ((st = run_onebody(b, nrhs, q, P, g, cf, s)) != FH_OK) return st;
+            const int nb = launch_dot_re(g, Z, b->total, nrhs, q, b->d_partial, s);
+            launch_reduce_partials(b->d_partial, 1, nb, 1, 1, b->d_small, 0, s);
+            FH_HIP(hipGetLastError());
+            FH_HIP(hipMemcpyAsync(&dJ_dLambda[q], b->d_small, sizeof(double), hipMemcpyDeviceToHost, s));
+            FH_HIP(hipStreamSynchronize(s));
+        }
+        return FH_OK;
+    });
+}
+
 fh_status fh_coherent_vjp(const fh_basis* b, int nrhs, const fh_c64* alpha, const fh_c64* lambda0, double* d_re,
                           double* d_im, void* stream) {
     return Guard::run([&]() -> fh_status {

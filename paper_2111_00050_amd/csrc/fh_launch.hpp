@@ -76,6 +76,12 @@ void launch_set_c64(double* p, long long idx, double re, double im, hipStream_t 
 // out[g*nvals + o] (+)= sum_{b<G} part[(g*G + b)*stride + o], fixed order.
 void launch_reduce_partials(const double* part, int ngroups, int G, int stride, int nvals, double* out,
                             int accumulate, hipStream_t s);
+// One RK4 stage of the tangent d psi/d Lambda (n complex entries; see util.hip).
+void launch_tangent_stage(const double* hz, const double* gy, const double* base, double* acc, double* next,
+                          double* baseout, long long n, int mode, double a, double c0, double b, hipStream_t s);
+// Re sum conj(g) z over column rhs: writes per-block partials, returns their count.
+int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
+                  hipStream_t s);
 // psi[i*nrhs + q] *= scale[q]
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s);
 

@@ -40,6 +40,50 @@ __global__ void scale_rhs_kernel(double* psi, long long total, int nrhs, const d
     }
 }
 
+// RK4 stage of the tangent z = d psi / d Lambda:  k = -i (hz + gy) with
+// hz = H z_s and gy = G y_s already applied; epilogue as in the fused stage:
+//   FIRST: acc = base + a k, next = c0 base + b k;  MID: acc += a k,
+//   next = c0 base + b k;  LAST: baseout = acc + a k.   (n complex entries)
+__global__ void tangent_stage_kernel(const double* hz, const double* gy, const double* base, double* acc,
+                                     double* next, double* baseout, long long n, int mode, double a, double c0,
+                                     double b) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double kr = hz[2 * i + 1] + gy[2 * i + 1];      // -i (x + i y) = y - i x
+        const double ki = -(hz[2 * i] + gy[2 * i]);
+        if (mode == kLast) {
+            baseout[2 * i] = fma(a, kr, acc[2 * i]);
+            baseout[2 * i + 1] = fma(a, ki, acc[2 * i + 1]);
+            continue;
+        }
+        const double br = base[2 * i], bi = base[2 * i + 1];
+        const double ar = mode == kFirst ? br : acc[2 * i], ai = mode == kFirst ? bi : acc[2 * i + 1];
+        acc[2 * i] = fma(a, kr, ar);
+        acc[2 * i + 1] = fma(a, ki, ai);
+        next[2 * i] = fma(b, kr, c0 * br);
+        next[2 * i + 1] = fma(b, ki, c0 * bi);
+    }
+}
+
+// Per-block partial sums of Re sum_i conj(g_i) z_i over column rhs of a
+// [total][nrhs] complex layout; partial[blockIdx.x] (fixed-order tree in the block).
+__global__ void dot_re_kernel(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial) {
+    __shared__ double red[256];
+    double s = 0.0;
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        const long long e = i * nrhs + rhs;
+        s = fma(g[2 * e], z[2 * e], fma(g[2 * e + 1], z[2 * e + 1], s));
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
 static unsigned grid_for(long long n) {
     long long b = (n + 255) / 256;
     if (b > 65536) b = 65536;
@@ -59,6 +103,18 @@ void launch_reduce_partials(const double* part, int ngroups, int G, int stride, 
     if (n > 0)
         hipLaunchKernelGGL(reduce_partials_kernel, dim3((n + 63) / 64), dim3(64), 0, s, part, ngroups, G, stride,
                            nvals, out, accumulate);
+}
+void launch_tangent_stage(const double* hz, const double* gy, const double* base, double* acc, double* next,
+                          double* baseout, long long n, int mode, double a, double c0, double b, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(tangent_stage_kernel, dim3(grid_for(n)), dim3(256), 0, s, hz, gy, base, acc, next, baseout,
+                           n, mode, a, c0, b);
+}
+int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
+                  hipStream_t s) {
+    const int G = 1024;
+    hipLaunchKernelGGL(dot_re_kernel, dim3(G), dim3(256), 0, s, g, z, total, nrhs, rhs, partial);
+    return G;
 }
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s) {
     if (total > 0)

@@ -442,3 +442,37 @@ def test_classical_equals_quantum_mean_without_interaction():
     aT, _ = fh.classical_rk4(model, alpha, dt, nsteps)
     # the truncated coherent state keeps 1 - n2 ~ 1e-9 of its norm outside the sectors
     assert np.abs(a_q / n2 - aT.cpu().numpy()[0]).max() <= 1e-8
+
+
+# ---------------------------------------------------- forward-mode tangent ---
+def test_tangent_dlambda_matches_adjoint():
+    """Forward-mode d/dLambda of the RK4 map gives the same dJ/dLambda as the
+    oracle's discrete adjoint (pinned by P12) and as the GPU adjoint."""
+    M, Lam, dt, nsteps = 3, 0.35, 5e-3, 30
+    sectors = W.all_sectors(M, 9)
+    omega = W.omega_quadratic(M)
+    V = W.V_longrange(M) + 0.3 * W.V_contact(M)
+    alpha = W.coherent_amplitudes(31, M, 1.5)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    psi0o = states.coherent_state(orc, alpha)
+    for obj, mk in ((fh.FH_J_Q, evolve.objective_Q), (fh.FH_J_PO, evolve.objective_PO),
+                    (fh.FH_J_NMODE, lambda o: evolve.objective_mode_occupation(o, 1))):
+        ref = evolve.adjoint(orc, psi0o, dt, nsteps, mk(orc))
+        psi0 = fh.init_coherent(b, alpha)
+        tan = fh.tangent_rk4(model, b, psi0, dt, nsteps, obj, mode=1)
+        assert abs(tan["J"][0] - ref["J"]) <= 1e-10
+        assert abs(tan["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
+        adj = fh.adjoint_rk4(model, b, psi0, dt, nsteps, 7, obj, mode=1)
+        assert abs(tan["dLambda"][0] - adj["dLambda"][0]) <= 1e-10 * max(1, abs(adj["dLambda"][0]))
+
+
+def test_tangent_two_rhs():
+    M, Lam, dt, nsteps = 4, 0.3, 5e-3, 12
+    b = fh.Basis(M, W.all_sectors(M, 8))
+    model = fh.Model(M, W.omega_quadratic(M), Lam, W.V_longrange(M))
+    al = np.stack([W.coherent_amplitudes(s, M, 1.3) for s in (61, 62)])
+    both = fh.tangent_rk4(model, b, fh.init_coherent(b, al), dt, nsteps, fh.FH_J_Q)
+    for q in range(2):
+        one = fh.tangent_rk4(model, b, fh.init_coherent(b, al[q]), dt, nsteps, fh.FH_J_Q)
+        assert abs(both["J"][q] - one["J"][0]) <= 1e-14
+        assert abs(both["dLambda"][q] - one["dLambda"][0]) <= 1e-12 * max(1.0, abs(one["dLambda"][0]))
