@@ -1217,17 +1217,16 @@ int class_rank(int M, int i, int j) {
     return -1;
 }
 
-fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* u, double uscale, const double* y,
-                   double* gtotal, hipStream_t s) {
+// gtotal += correlators of the kCorrPairs pairs (uscale[q] u[q], y[q]) for column rhs.
+fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u)[kCorrPairs],
+                   const double (&uscale)[kCorrPairs], const double* const (&y)[kCorrPairs], double* gtotal,
+                   hipStream_t s) {
     const int nt = (int)b->tiles.size();
     if (nt == 0) return FH_OK;
     const int M = b->M;
     const int NV = 2 * max_class_size(M) * max_class_size(M);
     const size_t lds = lds_bytes(b, 4 * NV);
     CorrArgs a{};
-    a.u = u;
-    a.y = y;
-    a.uscale = uscale;
     a.nrhs = nrhs;
     a.rhs = rhs;
     a.T = b->d_T;
@@ -1242,10 +1241,18 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* u, double
     a.xcd_order = b->xcd_order;
     a.occ = b->d_occ;
     const int G = persistent_grid(b, b->ks->corr_fn, lds, nt);
-    b->ks->corr(a, G, M, lds, s);  // one row of workgroups per momentum class
-    FH_HIP(hipGetLastError());
-    launch_reduce_partials(b->d_partial, M, G, 2 * kCorrOutMax, 2 * kCorrOutMax, gtotal, 1, s);
-    FH_HIP(hipGetLastError());
+    const int per = corr_pairs_per_launch(M);
+    for (int p0 = 0; p0 < kCorrPairs; p0 += per) {
+        for (int q = 0; q < per; ++q) {
+            a.u[q] = u[p0 + q];
+            a.y[q] = y[p0 + q];
+            a.uscale[q] = uscale[p0 + q];
+        }
+        b->ks->corr(a, G, M, lds, s);  // one row of workgroups per momentum class
+        FH_HIP(hipGetLastError());
+        launch_reduce_partials(b->d_partial, M, G, 2 * kCorrOutMax, 2 * kCorrOutMax, gtotal, 1, s);
+        FH_HIP(hipGetLastError());
+    }
     return FH_OK;
 }
 
@@ -1392,6 +1399,7 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         double* gacc = buf(sb + 6);
         double* kbA = buf(sb + 7);
         double* kbB = buf(sb + 8);
+        double* kbC = buf(sb + 9);
         double* g = reinterpret_cast<double*>(lambda0);
 
         fh_model* mT = nullptr;
@@ -1462,8 +1470,8 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         StageArgs b4 = ab, b3 = ab, b2 = ab, b1 = ab;
         b4.x = g; b4.mode = kFirst; b4.ks_im = dt / 6; b4.a = 1; b4.c0 = dt / 3; b4.b = dt; b4.ynext = kbA;
         b3.x = kbA; b3.mode = kMid; b3.a = 1; b3.c0 = dt / 3; b3.b = dt / 2; b3.ynext = kbB;
-        b2.x = kbB; b2.mode = kMid; b2.a = 1; b2.c0 = dt / 6; b2.b = dt / 2; b2.ynext = kbA;
-        b1.x = kbA; b1.mode = kLast; b1.a = 1; b1.baseout = g;
+        b2.x = kbB; b2.mode = kMid; b2.a = 1; b2.c0 = dt / 6; b2.b = dt / 2; b2.ynext = kbC;
+        b1.x = kbC; b1.mode = kLast; b1.a = 1; b1.baseout = g;
 
 
         for (int64_t k = nseg - 1; k >= 0; --k) {
@@ -1489,26 +1497,21 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
                     st = step(ps, nullptr, y2, y3, y4, 3);
                     if (st != FH_OK) return st;
                 }
-                // reverse stages (transposed model) and parameter correlators
-                st = launch_stage(b, nrhs, b4, 0, s, nullptr);
-                if (st != FH_OK) return st;
-                for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, g, dt / 6, s4p, gtot + q * gt_per, s);
+                // reverse stages (transposed model): kb4 -> kbA, kb3 -> kbB,
+                // kb2 -> kbC, then the correlators of all four stages in one
+                // pass (the step's g is still intact), then the last stage.
+                for (StageArgs* a : {&b4, &b3, &b2}) {
+                    st = launch_stage(b, nrhs, *a, 0, s, nullptr);
                     if (st != FH_OK) return st;
                 }
-                st = launch_stage(b, nrhs, b3, 0, s, nullptr);
-                if (st != FH_OK) return st;
-                for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, kbA, 1.0, s3p, gtot + q * gt_per, s);
-                    if (st != FH_OK) return st;
-                }
-                st = launch_stage(b, nrhs, b2, 0, s, nullptr);
-                if (st != FH_OK) return st;
-                for (int q = 0; q < nrhs; ++q) {
-                    st = run_corr(b, nrhs, q, kbB, 1.0, s2p, gtot + q * gt_per, s);
-                    if (st != FH_OK) return st;
-                    st = run_corr(b, nrhs, q, kbA, 1.0, ps, gtot + q * gt_per, s);
-                    if (st != FH_OK) return st;
+                {
+                    const double* us[kCorrPairs] = {g, kbA, kbB, kbC};
+                    const double sc[kCorrPairs] = {dt / 6, 1.0, 1.0, 1.0};
+                    const double* ys[kCorrPairs] = {s4p, s3p, s2p, ps};
+                    for (int q = 0; q < nrhs; ++q) {
+                        st = run_corr(b, nrhs, q, us, sc, ys, gtot + q * gt_per, s);
+                        if (st != FH_OK) return st;
+                    }
                 }
                 st = launch_stage(b, nrhs, b1, 0, s, nullptr);
                 if (st != FH_OK) return st;

@@ -200,13 +200,17 @@ struct OccArgs {
     unsigned char* occ;
 };
 
-// Quartic correlators  G[c][(p1,p2)] = sum_n conj(u(n)) <n|a_i^+ a_j^+ a_k a_l|n'> y(n')
-// for pairs p1 = {i,j}, p2 = {k,l} of class c (p1 == p2 included).
+// Quartic correlators  G[c][(p1,p2)] = sum_q sum_n conj(uscale_q u_q(n)) <n|a_i^+ a_j^+ a_k a_l|n'> y_q(n')
+// for pairs p1 = {i,j}, p2 = {k,l} of class c (p1 == p2 included), summed over
+// kCorrPairs vector pairs (u_q, y_q) at once (the four stages of an adjoint step).
+constexpr int kCorrPairs = 4;
+// pairs handled by one correlator launch (registers: M >= 9 has classes of 6 pairs)
+constexpr FH_HD int corr_pairs_per_launch(int M) { return M >= 9 ? 2 : kCorrPairs; }
 struct CorrArgs {
     const unsigned char* occ;  // occupation records
-    const double* u;
-    const double* y;
-    double uscale;      // u is used as uscale * u
+    const double* u[kCorrPairs];
+    const double* y[kCorrPairs];
+    double uscale[kCorrPairs];
     int nrhs, rhs;
     const int* T;
     int Tn, Rdim;

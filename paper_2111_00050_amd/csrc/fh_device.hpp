@@ -641,29 +641,40 @@ __global__ __launch_bounds__(kTileRows) void occ_table_kernel(OccArgs A) {
     }
 }
 
-// G[r1 * S + r2] += sum_n conj(uscale u(n)) <n| a_i^+ a_j^+ a_k a_l |n'> y(n')
+// G[r1 * S + r2] += sum_q sum_n conj(uscale_q u_q(n)) <n| a_i^+ a_j^+ a_k a_l |n'> y_q(n')
 // for the pairs p1 = member(C, r1) = {i,j}, p2 = member(C, r2) = {k,l} of one
-// momentum class C, n' = n - e_i - e_j + e_k + e_l (n' = n when r1 == r2).
-// One body per class keeps exactly that class's S^2 complex sums in
-// registers across the persistent tile loop; rows start from their
-// occupation records.  Partials are written with row stride max_class_size.
+// momentum class C, n' = n - e_i - e_j + e_k + e_l (n' = n when r1 == r2),
+// over the kCorrPairs vector pairs (u_q, y_q).  The pairs share the row's setup
+// and every neighbour rank; their terms go into the same sums.  One body per
+// class keeps exactly that class's S^2 complex sums in registers across the
+// persistent tile loop; rows start from their occupation records.  Partials
+// are written with row stride max_class_size.
 template <int M, int C>
 __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     using CB = Combos<M>;
     constexpr int S = CB::class_size(C);
     constexpr int SMAX = CB::max_class_size();
     constexpr int NV = 2 * S * S;
+    constexpr int NPR = corr_pairs_per_launch(M);  // the launch's pairs are u[0..NPR), y[0..NPR)
     extern __shared__ int smem[];
     int* sT = smem;
     double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
     double* red = sSq + A.nsqrt;
     stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
-    const double2* __restrict__ U = reinterpret_cast<const double2*>(A.u);
-    const double2* __restrict__ Y = reinterpret_cast<const double2*>(A.y);
     const int nrhs = A.nrhs, rhs = A.rhs;
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
+    // conj(u) y summed over the pairs
+    auto cdot = [](const double2 (&u)[NPR], const double2 (&y)[NPR], double& tr, double& ti) {
+        tr = 0.0;
+        ti = 0.0;
+#pragma unroll
+        for (int p = 0; p < NPR; ++p) {
+            tr = fma(u[p].x, y[p].x, fma(u[p].y, y[p].y, tr));
+            ti = fma(u[p].x, y[p].y, fma(-u[p].y, y[p].x, ti));
+        }
+    };
     const int vb = virtual_block(A.xcd_order);
     for (int t = vb; t < A.ntiles; t += gridDim.x) {
         const Tile tl = A.tiles[t];
@@ -675,9 +686,14 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
         load_occ<M>(A.occ, state, n);
         int key[M], Cs[M];
         row_keys<M>(sT, A.Rdim, n, key, Cs);
-        double2 u = U[state * nrhs + rhs];
-        u.x *= A.uscale;
-        u.y *= A.uscale;
+        double2 u[NPR], y0[NPR];
+#pragma unroll
+        for (int p = 0; p < NPR; ++p) {
+            u[p] = reinterpret_cast<const double2*>(A.u[p])[state * nrhs + rhs];
+            u[p].x *= A.uscale[p];
+            u[p].y *= A.uscale[p];
+            y0[p] = reinterpret_cast<const double2*>(A.y[p])[state * nrhs + rhs];
+        }
         double cij[S], ckl[S];
         static_for<0, S>([&](auto R1) {
             constexpr int r1 = decltype(R1)::value;
@@ -693,8 +709,8 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
         });
         {
             // p1 == p2: <n|a_i^+ a_j^+ a_i a_j|n> = c_ij^2
-            const double2 y = Y[state * nrhs + rhs];
-            const double tr = u.x * y.x + u.y * y.y, ti = u.x * y.y - u.y * y.x;
+            double tr, ti;
+            cdot(u, y0, tr, ti);
             static_for<0, S>([&](auto R1) {
                 constexpr int r1 = decltype(R1)::value;
                 constexpr int o = 2 * (r1 * S + r1);
@@ -704,11 +720,12 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
             });
         }
         if constexpr (S > 1) {
-            // Off-diagonal pairs in chunks: neighbour ranks, then the gathers
-            // in flight together, then the sums.  Lanes whose row pair is
-            // empty (c_ij == 0) gather their own row and add zero.
+            // Off-diagonal pairs in chunks: neighbour ranks (shared by the
+            // vector pairs), then the gathers in flight together, then the sums.
+            // Lanes whose row pair is empty (c_ij == 0) gather their own row
+            // and add zero.
             constexpr int NQ = S * (S - 1);
-            constexpr int QB = S >= 5 ? kGatherBatch / 2 : kGatherBatch;
+            constexpr int QB = S >= 5 ? kGatherBatch / (2 * NPR) : kGatherBatch / NPR;
             constexpr int NCH = (NQ + QB - 1) / QB;
             static_for<0, NCH>([&](auto Ch) {
                 constexpr int q0 = decltype(Ch)::value * QB;
@@ -730,16 +747,21 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
                     const int src = cij[r1] != 0.0 ? r : row;
                     off[decltype(Q)::value] = (sc.off + src) * nrhs + rhs;
                 });
-                double2 v[NQC];
-                static_for<0, NQC>([&](auto Q) { v[decltype(Q)::value] = Y[off[decltype(Q)::value]]; });
+                double2 v[NQC][NPR];
+                static_for<0, NQC>([&](auto Q) {
+#pragma unroll
+                    for (int p = 0; p < NPR; ++p)
+                        v[decltype(Q)::value][p] = reinterpret_cast<const double2*>(A.y[p])[off[decltype(Q)::value]];
+                });
                 static_for<0, NQC>([&](auto Q) {
                     constexpr int q = q0 + decltype(Q)::value;
                     constexpr int r1 = q / (S - 1), tq = q % (S - 1), r2 = tq < r1 ? tq : tq + 1;
                     constexpr int o = 2 * (r1 * S + r2);
-                    const double2 y = v[decltype(Q)::value];
+                    double tr, ti;
+                    cdot(u, v[decltype(Q)::value], tr, ti);
                     const double w = cij[r1] * ckl[r2];
-                    acc[o] = fma(w, u.x * y.x + u.y * y.y, acc[o]);
-                    acc[o + 1] = fma(w, u.x * y.y - u.y * y.x, acc[o + 1]);
+                    acc[o] = fma(w, tr, acc[o]);
+                    acc[o + 1] = fma(w, ti, acc[o + 1]);
                 });
                 asm volatile("" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
