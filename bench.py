@@ -41,15 +41,19 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(states: int):
+def measured_traffic(states: int, launch: dict):
     """HBM bytes per stage launch from committed rocprofv3 PMC counters, if
-    they were taken on the current kernel source."""
+    they were taken on the current kernel source with the same launch
+    schedule."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("kernel_sha") != kernel_hash() or t.get("states") != states:
+        return None
+    keys = ("blocks_per_cu", "xcd_order", "tile_order", "prefix_modes")
+    if any(t.get("launch", {}).get(k) != launch.get(k) for k in keys):
         return None
     return t.get("bytes_per_launch")
 
@@ -237,6 +241,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / multi-rhs / adjoint comparisons")
     ap.add_argument("--forms-only", action="store_true", help="run only the form comparisons (one JSON object)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the launch schedule given by the next four options instead of the autotuner's")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--xcd-order", type=int, default=1)
     ap.add_argument("--tile-order", type=int, default=0)
@@ -260,10 +266,18 @@ def main():
     w = W.large_sector()
     model = fh.Model(w.M, w.omega, w.Lambda, w.V)
     basis = fh.Basis(w.M, w.sectors)
-    basis.set_launch(args.blocks_per_cu, args.xcd_order)
-    basis.set_tile_order(args.tile_order, args.prefix_modes)
     D = basis.total
     psi = fh.init_number(basis, w.init_params)
+    if args.no_autotune:
+        basis.set_launch(args.blocks_per_cu, args.xcd_order)
+        basis.set_tile_order(args.tile_order, args.prefix_modes)
+        launch = {"blocks_per_cu": args.blocks_per_cu, "xcd_order": args.xcd_order,
+                  "tile_order": args.tile_order, "prefix_modes": args.prefix_modes, "autotuned": False}
+    else:
+        # untimed: pick the launch schedule of the stage kernel for this basis
+        launch, _ = fh.autotune(model, basis, psi)
+        launch["autotuned"] = True
+        print(f"[bench] autotuned launch {launch}", file=sys.stderr, flush=True)
     work = torch.empty(3 * D, dtype=torch.complex128, device="cuda")
     print(f"[bench] {w.name}: {D} states; warmup {args.warmup} steps", file=sys.stderr, flush=True)
     if args.warmup > 0:
@@ -278,7 +292,7 @@ def main():
     avg_stage_s = res.stage_ms / 1e3 / max(1, res.stage_launches)
     alg_bytes = STAGE_BYTES_PER_STATE * D
     achieved = alg_bytes / avg_stage_s / 1e9
-    traffic = measured_traffic(D)
+    traffic = measured_traffic(D, launch)
     norms = res.records[:, 0, 0]
     obs0 = fh.derive(w.M, *fh.unpack_moments(w.M, res.records[0, 0]))
     obsT = fh.derive(w.M, *fh.unpack_moments(w.M, res.records[-1, 0]))
@@ -302,6 +316,7 @@ def main():
             "parallelism": "single GPU",
         },
         "hpsi_per_s": 4.0 * steps_per_s,
+        "launch": launch,
         "stage_kernel_ms": 1e3 * avg_stage_s,
         "roofline": {
             "bound": "hbm",

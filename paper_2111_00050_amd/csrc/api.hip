@@ -655,7 +655,7 @@ fh_status fh_basis_sizes(const fh_basis* b, int64_t* dim, int64_t* offset) {
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order) {
     FH_REQUIRE(b != nullptr, FH_EINVAL, "fh_basis_set_launch: basis is NULL");
     FH_REQUIRE(blocks_per_cu >= 0 && blocks_per_cu <= 8, FH_EINVAL, "blocks_per_cu must be in [0, 8]");
-    FH_REQUIRE(xcd_order == 0 || xcd_order == 1, FH_EINVAL, "xcd_order must be 0 or 1");
+    FH_REQUIRE(xcd_order >= 0 && xcd_order <= 2, FH_EINVAL, "xcd_order must be 0, 1 or 2");
     b->blocks_per_cu = blocks_per_cu;
     b->xcd_order = xcd_order;
     return FH_OK;
@@ -960,7 +960,7 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
             std::vector<std::array<int, 4>> cands;
             const int maxp = std::min(b->M - 1, 3);
             for (int bpc : {0, 1, 2, 3})
-                for (int xo : {1, 0})
+                for (int xo : {2, 1, 0})
                     for (int pre = 0; pre <= maxp; ++pre) {
                         if (pre == 1) continue;  // a one-mode prefix never pays
                         cands.push_back({bpc, xo, pre > 0 ? 1 : 0, pre});

@@ -49,6 +49,26 @@ __device__ __forceinline__ int virtual_block(int xcd_order) {
     return b;
 }
 
+// The work units (tiles, or passes over tiles) a persistent workgroup walks:
+// first, first + step, ... < end.  Workgroups are dealt to the 8 XCDs round
+// robin (blockIdx.x mod 8).
+//   xcd_order 0: unit b, b + G, ...
+//   xcd_order 1: the XCDs take contiguous chunks of G/8 units in turn
+//   xcd_order 2: XCD x walks the x-th contiguous eighth of all units, so its
+//                L2 sees one sliding neighbourhood of the state vector
+struct UnitWalk {
+    int first, end, step;
+};
+__device__ __forceinline__ UnitWalk unit_walk(int xcd_order, int nunits) {
+    const int b = blockIdx.x, G = gridDim.x;
+    if (xcd_order == 2 && (G & 7) == 0) {
+        const int x = b & 7;
+        const int lo = (int)((long long)nunits * x / 8), hi = (int)((long long)nunits * (x + 1) / 8);
+        return UnitWalk{lo + (b >> 3), hi, G >> 3};
+    }
+    return UnitWalk{virtual_block(xcd_order == 0 ? 0 : 1), nunits, G};
+}
+
 template <int M>
 __device__ __forceinline__ int modM(int x) {
     x %= M;
@@ -223,7 +243,6 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
     const __attribute__((address_space(4))) double* cf =
         (const __attribute__((address_space(4))) double*)A.coef;
     const double2* X = reinterpret_cast<const double2*>(A.x);
-    const int vb = virtual_block(A.xcd_order);
     // With several right-hand sides, G lanes share a row and lane `sub` owns
     // the right-hand sides sub, sub + G, ...: every gather instruction then
     // reads 16*G contiguous bytes per row.  The row's index work is repeated
@@ -239,7 +258,8 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
     const __attribute__((address_space(4))) Tile* tiles = (const __attribute__((address_space(4))) Tile*)A.tiles;
     const __attribute__((address_space(4))) SecInfo* secs =
         (const __attribute__((address_space(4))) SecInfo*)A.secs;
-    for (int vt = vb; vt < A.ntiles * G; vt += gridDim.x) {
+    const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles * G);
+    for (int vt = walk.first; vt < walk.end; vt += walk.step) {
         const int tsec = __builtin_amdgcn_readfirstlane(tiles[vt / G].sec);
         const int row0 = __builtin_amdgcn_readfirstlane(tiles[vt / G].row0);
         const int nrows = __builtin_amdgcn_readfirstlane(tiles[vt / G].nrows);
@@ -473,8 +493,8 @@ __global__ __launch_bounds__(kTileRows) void moments_kernel(MomArgs A) {
         return true;
     };
 
-    const int vb = virtual_block(A.xcd_order);
-    for (int t = vb; t < A.ntiles; t += gridDim.x) {
+    const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles);
+    for (int t = walk.first; t < walk.end; t += walk.step) {
         const int tsec = __builtin_amdgcn_readfirstlane(tiles[t].sec);
         const int row0 = __builtin_amdgcn_readfirstlane(tiles[t].row0);
         const int nrows = __builtin_amdgcn_readfirstlane(tiles[t].nrows);
@@ -675,8 +695,8 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
             ti = fma(u[p].x, y[p].y, fma(-u[p].y, y[p].x, ti));
         }
     };
-    const int vb = virtual_block(A.xcd_order);
-    for (int t = vb; t < A.ntiles; t += gridDim.x) {
+    const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles);
+    for (int t = walk.first; t < walk.end; t += walk.step) {
         const Tile tl = A.tiles[t];
         if ((int)threadIdx.x >= tl.nrows) continue;
         const SecInfo sc = A.secs[tl.sec];
