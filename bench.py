@@ -41,6 +41,19 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def profiled_launch(states: int):
+    """Launch schedule recorded with the committed counters, if they were taken
+    on the current kernel source and this sector."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("states") != states or "launch" not in t:
+        return None
+    return dict(t["launch"])
+
+
 def measured_traffic(states: int, launch: dict):
     """HBM bytes per stage launch from committed rocprofv3 PMC counters, if
     they were taken on the current kernel source with the same launch
@@ -273,6 +286,13 @@ def main():
         basis.set_tile_order(args.tile_order, args.prefix_modes)
         launch = {"blocks_per_cu": args.blocks_per_cu, "xcd_order": args.xcd_order,
                   "tile_order": args.tile_order, "prefix_modes": args.prefix_modes, "autotuned": False}
+    elif profiled_launch(D) is not None:
+        # the schedule the autotuner chose when the committed counters were
+        # taken on this kernel source (so that 'traffic' applies to this run)
+        launch = profiled_launch(D)
+        basis.set_launch(launch["blocks_per_cu"], launch["xcd_order"])
+        basis.set_tile_order(launch["tile_order"], launch["prefix_modes"])
+        launch["autotuned"] = "when profiled"
     else:
         # untimed: pick the launch schedule of the stage kernel for this basis
         launch, _ = fh.autotune(model, basis, psi)
