@@ -13,8 +13,8 @@ its own Jacobi sweep).
 Modules:
   oracle              ctypes binding of ``fock_oracle.c`` (basis, H psi, moments)
   oracle.states       initial states of Sec. II.B
-  oracle.evolve       classical RK4, the paper's second-order step, and the
-                      discrete adjoint of the RK4 map
+  oracle.evolve       classical RK4, the paper's second-order step, the
+                      Chebyshev propagator, and the discrete adjoint of RK4
   oracle.derived      Q, Penrose-Onsager eigenvalue, squeezing V_-
   oracle.dense        dense-matrix references for sectors of <= ~500 states
   oracle.classical    mean-field (classical field) equations and their RK4

@@ -64,6 +64,49 @@ def taylor2(orc, psi0, dt, nsteps, c2=0.5, every=0, observe=None):
     return psi, out
 
 
+def chebyshev_terms(x, tol=1e-14):
+    """Number of terms K so that the Chebyshev series of exp(-i x T) (|T| <= 1)
+    keeps every coefficient 2 |J_k(x)| >= tol for k < K (J_k decays
+    super-exponentially once k > x)."""
+    from scipy.special import jv
+
+    k = int(x) + 1
+    while 2.0 * abs(jv(k, x)) >= tol or k <= x:
+        k += 1
+    return k + 1
+
+
+def chebyshev(orc, psi0, dt, nsteps, emin, emax, tol=1e-14, every=0, observe=None):
+    """Exact-exponential steps psi <- exp(-i H dt) psi by the Chebyshev series
+    (spectrum of H inside [emin, emax]):
+        H = a + b T,  a = (emax + emin)/2,  b = (emax - emin)/2,
+        exp(-i H dt) = exp(-i a dt) sum_k c_k T_k(T),
+        c_0 = J_0(b dt),  c_k = 2 (-i)^k J_k(b dt),
+        T_0 psi = psi, T_1 psi = T psi, T_{k+1} psi = 2 T T_k psi - T_{k-1} psi.
+    Outputs as in rk4()."""
+    from scipy.special import jv
+
+    a, b = 0.5 * (emax + emin), 0.5 * (emax - emin)
+    K = chebyshev_terms(b * dt, tol)
+    c = np.array([(1.0 if k == 0 else 2.0) * (-1j) ** k * jv(k, b * dt) for k in range(K)])
+    phase = np.exp(-1j * a * dt)
+    T = lambda v: (orc.apply_h(v) - a * v) / b
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    out = []
+    for s in range(nsteps + 1):
+        if every > 0 and s % every == 0 and observe is not None:
+            out.append(observe(s, s * dt, psi))
+        if s == nsteps:
+            break
+        t_prev, t_cur = psi, T(psi)
+        acc = c[0] * t_prev + c[1] * t_cur
+        for k in range(2, K):
+            t_prev, t_cur = t_cur, 2.0 * T(t_cur) - t_prev
+            acc = acc + c[k] * t_cur
+        psi = phase * acc
+    return psi, out
+
+
 def _stages(orc, psi, dt):
     f = lambda y: -1j * orc.apply_h(y)
     y1 = psi

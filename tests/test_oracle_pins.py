@@ -20,6 +20,8 @@ identity, a dense-matrix propagator, a printed number of the paper).
       Kerr rotations, invariants of the flow
   T1-T2 the paper's second-order step (Eq. Q_int): free factor 1 + z + c2 z^2,
       dense propagator, second order only with c2 = 1/2
+  X1-X2 Chebyshev propagator: equal to exp(-i H t) (dense expm) and to the
+      free phases exp(-i E t), at steps where RK4 is unstable
 """
 import itertools
 import math
@@ -466,3 +468,31 @@ def test_t2_taylor2_dense_propagator(oracle_lib):
     err_half = np.linalg.norm(psi - exact)
     psi1, _ = evolve.taylor2(o, psi0, w.dt, n, c2=1.0)
     assert err_half < 0.1 * np.linalg.norm(psi1 - exact)
+
+
+# ------------------------------------------------ Chebyshev propagator (X) ---
+def test_x1_chebyshev_equals_exponential(oracle_lib):
+    """The Chebyshev series reproduces exp(-i H t) psi0 (dense expm) at large
+    steps, where RK4 would be unstable (|E| dt > 2.8)."""
+    w = W.tiny_number()
+    o = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    psi0 = states.number_state(o, w.init_params)
+    H = dense.dense_h(o)
+    E = np.linalg.eigvalsh(H)
+    emin, emax = E.min() - 0.5, E.max() + 0.5
+    dt, n = 0.7, 5
+    assert max(abs(emin), abs(emax)) * dt > 2.8
+    psi, _ = evolve.chebyshev(o, psi0, dt, n, emin, emax)
+    np.testing.assert_allclose(psi, dense.expm_evolve(H, psi0, n * dt), rtol=0, atol=1e-12)
+
+
+def test_x2_chebyshev_free_phases(oracle_lib):
+    """Lambda = 0: each amplitude picks up exp(-i E t) exactly."""
+    M, dt, n = 4, 0.9, 4
+    sectors = [(6, p) for p in range(M)]
+    om = W.omega_quadratic(M)
+    o = Oracle(M, M, om, 0.0, W.V_contact(M), sectors)
+    psi0 = W.random_psi(o.total, 5)
+    E = o.all_occupations() @ om
+    psi, _ = evolve.chebyshev(o, psi0, dt, n, -1.0, E.max() + 1.0)
+    np.testing.assert_allclose(psi, psi0 * np.exp(-1j * E * n * dt), rtol=0, atol=1e-12)
