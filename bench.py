@@ -118,6 +118,9 @@ def forms():
                   state, mean 20, 331 sectors, 100 steps; one M=10 field-number
                   draw, 212M states, 10 steps), with a central difference of
                   J in Lambda on the first.
+      chebyshev : the Chebyshev propagator (exp(-i H dt) to 1e-14 per step, steps
+                  of 0.05) vs RK4 at the bench's dt = 5e-4 over t = 0.2 on the
+                  bench's sector; their difference is RK4's truncation error.
     Equal-accuracy check: the two paths of a pair return the same amplitudes
     (max |difference| is reported; the kernels sum in the same order)."""
     import numpy as np
@@ -196,6 +199,35 @@ def forms():
         "max_abs_diff_draw0": float((psi1 - col0).abs().max()),
     }
     del psi1, work1, col0
+    model.close()
+    basis.close()
+    torch.cuda.empty_cache()
+
+    # ---- Chebyshev propagator vs RK4 over the same simulated time
+    w = W.large_sector()
+    model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    log(f"chebyshev: {w.name}, {basis.total} states")
+    T, cdt = 0.2, 0.05
+    psi0 = fh.init_number(basis, w.init_params)
+    p_r = psi0.clone()
+    _, t_rk4 = timed(lambda: fh.evolve_rk4(model, basis, p_r, w.dt, int(round(T / w.dt))))
+    rho, t_rho = timed(lambda: fh.spectral_radius(model, basis, iters=60))
+    R = 1.1 * rho + 1e-9
+    p_c = psi0.clone()
+    _, t_ch = timed(lambda: fh.evolve_chebyshev(model, basis, p_c, cdt, int(round(T / cdt)), -R, R))
+    p_h = psi0.clone()
+    fh.evolve_chebyshev(model, basis, p_h, cdt / 2, int(round(2 * T / cdt)), -R, R)
+    nrm = float(torch.linalg.vector_norm(p_h))
+    out["chebyshev"] = {
+        "workload": w.name + f", evolved to t = {T}",
+        "states": basis.total, "rk4_dt": w.dt, "chebyshev_dt": cdt, "spectral_interval": [-R, R],
+        "rk4_s": t_rk4, "chebyshev_s": t_ch, "spectral_radius_s": t_rho, "speedup": t_rk4 / (t_ch + t_rho),
+        "terms_per_step": int(len(fh.chebyshev_coefficients(R * cdt))),
+        "rel_diff_rk4_vs_chebyshev": float(torch.linalg.vector_norm(p_r - p_c)) / nrm,
+        "rel_diff_chebyshev_step_halved": float(torch.linalg.vector_norm(p_c - p_h)) / nrm,
+    }
+    log(f"  rk4 {t_rk4:.2f} s, chebyshev {t_ch:.2f} s + bound {t_rho:.2f} s")
+    del psi0, p_r, p_c, p_h
     model.close()
     basis.close()
     torch.cuda.empty_cache()

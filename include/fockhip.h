@@ -252,6 +252,31 @@ fh_status fh_classical_rk4(const fh_model* m, int ntraj, fh_c64* alpha, double d
 #define FH_J_Q 0
 #define FH_J_PO 1
 #define FH_J_NMODE 2
+/* Chebyshev propagator: nsteps steps psi <- exp(-i H dt) psi (Sec. II.A,
+ * d|phi>/dt = -i H |phi>), exact up to the series truncation tol, by
+ *   H = a + b T, a = (emax + emin)/2, b = (emax - emin)/2,
+ *   exp(-i H dt) = exp(-i a dt) sum_k c_k T_k(T),  c_0 = J_0(b dt), c_k = 2 (-i)^k J_k(b dt),
+ * with the three-term recurrence of the Chebyshev polynomials (one H psi per
+ * term).  The spectrum of H on the basis must lie in [emin, emax] (see
+ * fh_spectral_radius); the call fails with FH_ESTATE when the norm is not
+ * conserved to 1e-8, the sign of an interval that is too small.  Time steps
+ * may be far beyond RK4's stability limit.  work: device scratch of
+ * 4*total*nrhs fh_c64.  Moments, FH_PER_SECTOR and FH_TIMING as for
+ * fh_evolve_rk4 (FH_GRAPH is not supported). */
+fh_status fh_evolve_chebyshev(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work, double dt,
+                              int64_t nsteps, double emin, double emax, double tol, int64_t obs_every,
+                              double* moments, int64_t moments_capacity, int flags, fh_timing* timing,
+                              void* stream);
+/* Coefficients c_k (re, im; arrays of kmax) of that series for x = b dt and
+ * their number K: the first k > x with 2 |J_k(x)| < tol, plus one.  Host
+ * only; returns -1 if the arguments are invalid or K would exceed kmax. */
+int fh_chebyshev_coefficients(double x, double tol, int kmax, double* c_re, double* c_im);
+/* Estimate of the spectral radius max |E| of H on the basis by 'iters' power
+ * iterations from a fixed pseudo-random vector (SplitMix64 of the index);
+ * a lower bound that converges to max |E|.  work: 2*total fh_c64 (device). */
+fh_status fh_spectral_radius(const fh_model* m, const fh_basis* b, fh_c64* work, int iters, double* rho,
+                             void* stream);
+
 /* Forward-mode tangent of the RK4 map with respect to Lambda: evolves psi
  * and dpsi = d psi/d Lambda together for nsteps steps (in place; dpsi is
  * usually zero at the start),

@@ -74,6 +74,9 @@ SIGNATURES = {
     "fh_evolve_taylor2": (_I, [_P, _P, _I, _P, _P, _D, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_classical_rk4": (_I, [_P, _I, _P, _D, _I64, _I64, _P, _P]),
     "fh_tangent_rk4": (_I, [_P, _P, _I, _P, _P, _P, _D, _I64, _I, _I, _P, _P, _P]),
+    "fh_evolve_chebyshev": (_I, [_P, _P, _I, _P, _P, _D, _I64, _D, _D, _D, _I64, _P, _I64, _I, _P, _P]),
+    "fh_chebyshev_coefficients": (_I, [_D, _D, _I, _P, _P]),
+    "fh_spectral_radius": (_I, [_P, _P, _P, _I, _P, _P]),
     "fh_adjoint_work_states": (_I64, [_I64, _I64]),
     "fh_adjoint_work_states_kept": (_I64, [_I64, _I64]),
     "fh_adjoint_rk4": (_I, [_P, _P, _I, _P, _D, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
@@ -380,6 +383,50 @@ def evolve_taylor2(model, basis, psi, dt, nsteps, c2=0.5, every=0, flags=0, work
                                   _dev_ptr(work, torch.complex128, "work"), float(dt), float(c2), int(nsteps),
                                   int(every), _np_ptr(rec), rec.size if nrec else 0, int(flags), ctypes.byref(tm),
                                   _stream()))
+    steps = np.arange(nrec) * every if nrec else np.zeros(0, int)
+    return EvolveResult(rec[:nrec], steps, tm.stage_ms, tm.stage_launches, tm.wall_ms)
+
+
+def spectral_radius(model, basis, iters=100):
+    """Power-iteration estimate of max |E| of H on the basis (fh_spectral_radius)."""
+    torch = _torch()
+    work = torch.empty((2 * basis.total,), dtype=torch.complex128, device="cuda")
+    rho = ctypes.c_double(0.0)
+    _check(_lib.fh_spectral_radius(model.handle, basis.handle, _dev_ptr(work, torch.complex128, "work"), int(iters),
+                                   ctypes.byref(rho), _stream()))
+    return float(rho.value)
+
+
+def chebyshev_coefficients(x, tol=1e-14, kmax=4096):
+    """Series coefficients c_k of exp(-i x T) (fh_chebyshev_coefficients), complex array."""
+    re = np.zeros(kmax)
+    im = np.zeros(kmax)
+    K = _lib.fh_chebyshev_coefficients(float(x), float(tol), int(kmax), _np_ptr(re), _np_ptr(im))
+    if K < 0:
+        raise ValueError("invalid arguments or too many terms")
+    return re[:K] + 1j * im[:K]
+
+
+def evolve_chebyshev(model, basis, psi, dt, nsteps, emin=None, emax=None, tol=1e-14, every=0, flags=0, work=None,
+                     margin=1.1):
+    """nsteps exact-exponential steps exp(-i H dt) in place on psi by the Chebyshev series
+    (fh_evolve_chebyshev).  Without bounds, [emin, emax] = [-r, r] with r = margin times
+    the power-iteration spectral radius."""
+    torch = _torch()
+    nrhs = _nrhs_of(basis, psi)
+    if emin is None or emax is None:
+        r = margin * spectral_radius(model, basis) + 1e-9
+        emin, emax = -r, r
+    if work is None:
+        work = torch.empty((4 * basis.total * nrhs,), dtype=torch.complex128, device=psi.device)
+    M = basis.M
+    nrec = nsteps // every + 1 if every > 0 else 0
+    rec = np.zeros((max(nrec, 1), nrhs, moment_doubles(M)))
+    tm = fh_timing()
+    _check(_lib.fh_evolve_chebyshev(model.handle, basis.handle, nrhs, _dev_ptr(psi, torch.complex128, "psi"),
+                                    _dev_ptr(work, torch.complex128, "work"), float(dt), int(nsteps), float(emin),
+                                    float(emax), float(tol), int(every), _np_ptr(rec), rec.size if nrec else 0,
+                                    int(flags), ctypes.byref(tm), _stream()))
     steps = np.arange(nrec) * every if nrec else np.zeros(0, int)
     return EvolveResult(rec[:nrec], steps, tm.stage_ms, tm.stage_launches, tm.wall_ms)
 

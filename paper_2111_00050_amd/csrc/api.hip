@@ -1636,6 +1636,162 @@ fh_status fh_tangent_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64*
     });
 }
 
+int fh_chebyshev_coefficients(double x, double tol, int kmax, double* c_re, double* c_im) {
+    if (!std::isfinite(x) || x < 0.0 || !(tol > 0.0) || kmax < 2 || x >= (double)kmax) return -1;
+    int k = (int)x + 1;
+    while (k <= x || 2.0 * std::fabs(std::cyl_bessel_j((double)k, x)) >= tol) {
+        if (++k >= kmax) return -1;
+    }
+    const int K = k + 1;
+    if (K > kmax) return -1;
+    static const double pr[4] = {1.0, 0.0, -1.0, 0.0}, pi[4] = {0.0, -1.0, 0.0, 1.0};  // (-i)^j
+    for (int j = 0; j < K; ++j) {
+        const double J = (j == 0 ? 1.0 : 2.0) * std::cyl_bessel_j((double)j, x);
+        if (c_re) c_re[j] = pr[j & 3] * J;
+        if (c_im) c_im[j] = pi[j & 3] * J;
+    }
+    return K;
+}
+
+fh_status fh_spectral_radius(const fh_model* m, const fh_basis* b, fh_c64* work, int iters, double* rho,
+                             void* stream) {
+    return Guard::run([&]() -> fh_status {
+        if (!check_model_basis(m, b)) return FH_EINVAL;
+        FH_REQUIRE(work && rho && iters >= 1, FH_EINVAL, "fh_spectral_radius: bad argument");
+        hipStream_t s = as_stream(stream);
+        const int64_t vec = 2 * b->total;
+        double* x = reinterpret_cast<double*>(work);
+        double* y = x + vec;
+        auto norm2 = [&](const double* v, double* out) -> fh_status {
+            const int nb = launch_dot_re(v, v, b->total, 1, 0, b->d_partial, s);
+            launch_reduce_partials(b->d_partial, 1, nb, 1, 1, b->d_small, 0, s);
+            FH_HIP(hipGetLastError());
+            FH_HIP(hipMemcpyAsync(out, b->d_small, sizeof(double), hipMemcpyDeviceToHost, s));
+            FH_HIP(hipStreamSynchronize(s));
+            return FH_OK;
+        };
+        launch_hash_fill(x, b->total, 0x5eed5eedull, s);
+        double nx = 0.0, ny = 0.0, r = 0.0;
+        fh_status st = norm2(x, &nx);
+        if (st != FH_OK) return st;
+        FH_REQUIRE(nx > 0.0, FH_ESTATE, "fh_spectral_radius: empty basis");
+        for (int it = 0; it < iters; ++it) {
+            StageArgs a = stage_base(m, b);
+            a.x = x;
+            a.out = y;
+            a.mode = kApply;
+            if ((st = launch_stage(b, 1, a, 0, s, nullptr)) != FH_OK) return st;
+            if ((st = norm2(y, &ny)) != FH_OK) return st;
+            r = std::sqrt(ny / nx);
+            if (ny == 0.0) break;
+            launch_cscale(x, y, b->total, 1.0 / std::sqrt(ny), 0.0, s);
+            nx = 1.0;
+        }
+        *rho = r;
+        return FH_OK;
+    });
+}
+
+fh_status fh_evolve_chebyshev(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* work, double dt,
+                              int64_t nsteps, double emin, double emax, double tol, int64_t obs_every,
+                              double* moments, int64_t moments_capacity, int flags, fh_timing* timing,
+                              void* stream) {
+    return Guard::run([&]() -> fh_status {
+        const auto t0 = std::chrono::steady_clock::now();
+        if (!check_model_basis(m, b)) return FH_EINVAL;
+        FH_REQUIRE(!bad_nrhs(nrhs), FH_EINVAL, "nrhs must be 1, 2, 4, 8 or 16");
+        FH_REQUIRE(psi && work, FH_EINVAL, "fh_evolve_chebyshev: NULL buffer");
+        FH_REQUIRE(nsteps >= 0 && obs_every >= 0, FH_EINVAL, "fh_evolve_chebyshev: negative step count");
+        FH_REQUIRE(std::isfinite(dt) && dt >= 0.0, FH_EINVAL, "fh_evolve_chebyshev: dt must be finite and >= 0");
+        FH_REQUIRE(std::isfinite(emin) && std::isfinite(emax) && emax > emin, FH_EINVAL,
+                   "fh_evolve_chebyshev: need finite emin < emax");
+        FH_REQUIRE(tol > 0.0, FH_EINVAL, "fh_evolve_chebyshev: tol must be > 0");
+        FH_REQUIRE(!(flags & FH_GRAPH), FH_EINVAL, "fh_evolve_chebyshev: FH_GRAPH is not supported");
+        const int M = b->M;
+        hipStream_t s = as_stream(stream);
+        const double a = 0.5 * (emax + emin), bw = 0.5 * (emax - emin);
+        std::vector<double> cre(4096), cim(4096);  // up to 4096 terms: (emax - emin) dt / 2 < ~4000
+        const int K = fh_chebyshev_coefficients(bw * dt, tol, (int)cre.size(), cre.data(), cim.data());
+        FH_REQUIRE(K >= 2, FH_EUNSUPPORTED, "fh_evolve_chebyshev: (emax - emin) * dt too large for one step");
+        const int64_t vec = 2 * b->total * nrhs;
+        const long long ncplx = (long long)b->total * nrhs;
+        double* P = reinterpret_cast<double*>(psi);
+        double* A = reinterpret_cast<double*>(work);
+        double* B = A + vec;
+        double* h = A + 2 * vec;
+        double* acc = A + 3 * vec;
+        const int64_t nrec = obs_every > 0 ? nsteps / obs_every + 1 : 0;
+        const int64_t per = (int64_t)FH_MOMENT_DOUBLES(M) * nrhs;
+        if (nrec > 0) {
+            FH_REQUIRE(moments != nullptr, FH_EINVAL, "fh_evolve_chebyshev: moments buffer is NULL");
+            FH_REQUIRE(moments_capacity >= nrec * per, FH_ENOMEM, "fh_evolve_chebyshev: moments buffer too small");
+        }
+        StageTimer tm;
+        fh_status st = tm.init((flags & FH_TIMING) != 0, s);
+        if (st != FH_OK) return st;
+        StageTimer* tmp = (flags & FH_TIMING) ? &tm : nullptr;
+        auto norm2 = [&](double* out) -> fh_status {
+            const int nb = launch_dot_re(P, P, ncplx, 1, 0, b->d_partial, s);
+            launch_reduce_partials(b->d_partial, 1, nb, 1, 1, b->d_small, 0, s);
+            FH_HIP(hipGetLastError());
+            FH_HIP(hipMemcpyAsync(out, b->d_small, sizeof(double), hipMemcpyDeviceToHost, s));
+            FH_HIP(hipStreamSynchronize(s));
+            return FH_OK;
+        };
+        auto apply = [&](const double* x) -> fh_status {
+            StageArgs sa = stage_base(m, b);
+            sa.x = x;
+            sa.out = h;
+            sa.mode = kApply;
+            return launch_stage(b, nrhs, sa, flags, s, tmp);
+        };
+        auto record = [&](int64_t r) -> fh_status {
+            for (int q = 0; q < nrhs; ++q) {
+                fh_status e = run_moments(b, nrhs, q, P, moments + r * per + (int64_t)q * FH_MOMENT_DOUBLES(M), s,
+                                          M + 1);
+                if (e != FH_OK) return e;
+            }
+            return FH_OK;
+        };
+        double n0 = 0.0, n1 = 0.0;
+        if ((st = norm2(&n0)) != FH_OK) return st;
+        int64_t r = 0;
+        if (nrec > 0 && (st = record(r++)) != FH_OK) return st;
+        const double ph_re = std::cos(a * dt), ph_im = -std::sin(a * dt);
+        for (int64_t step = 1; step <= nsteps; ++step) {
+            // T_1 psi = (H - a) psi / b;  acc = c_0 psi + c_1 T_1 psi
+            if ((st = apply(P)) != FH_OK) return st;
+            launch_cheb_term(h, P, nullptr, B, acc, ncplx, 1.0 / bw, -a / bw, 0.0, cre[1], cim[1], 1, cre[0], cim[0], s);
+            const double* prev = P;
+            double* cur = B;
+            for (int k = 2; k < K; ++k) {
+                // T_k = 2 (H - a)/b T_{k-1} - T_{k-2}, written over T_{k-2} (never over psi)
+                if ((st = apply(cur)) != FH_OK) return st;
+                double* dest = prev == P ? A : const_cast<double*>(prev);
+                launch_cheb_term(h, cur, prev, dest, acc, ncplx, 2.0 / bw, -2.0 * a / bw, -1.0, cre[k], cim[k], 0, 0.0,
+                                 0.0, s);
+                prev = cur;
+                cur = dest;
+            }
+            launch_cscale(P, acc, ncplx, ph_re, ph_im, s);  // psi = exp(-i a dt) acc
+            FH_HIP(hipGetLastError());
+            if (obs_every > 0 && step % obs_every == 0 && (st = record(r++)) != FH_OK) return st;
+        }
+        st = tm.flush();
+        if (st != FH_OK) return st;
+        if ((st = norm2(&n1)) != FH_OK) return st;
+        // exp(-i H t) keeps the norm; a series that left [-1, 1] grows without bound
+        FH_REQUIRE(std::isfinite(n1) && std::fabs(n1 - n0) <= 1e-8 * std::max(n0, 1e-300), FH_ESTATE,
+                   "fh_evolve_chebyshev: norm not conserved; the spectrum of H is not inside [emin, emax]");
+        if (timing) {
+            timing->stage_ms = tm.ms;
+            timing->stage_launches = tm.launches;
+            timing->wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+        return FH_OK;
+    });
+}
+
 fh_status fh_coherent_vjp(const fh_basis* b, int nrhs, const fh_c64* alpha, const fh_c64* lambda0, double* d_re,
                           double* d_im, void* stream) {
     return Guard::run([&]() -> fh_status {

@@ -82,6 +82,12 @@ void launch_tangent_stage(const double* hz, const double* gy, const double* base
 // Re sum conj(g) z over column rhs: writes per-block partials, returns their count.
 int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
                   hipStream_t s);
+// Chebyshev term, complex scale and deterministic start vector (see util.hip).
+void launch_cheb_term(const double* h, const double* x, const double* prev, double* next, double* acc, long long n,
+                      double alpha, double beta, double gamma, double c_re, double c_im, int init, double c0_re,
+                      double c0_im, hipStream_t s);
+void launch_cscale(double* out, const double* in, long long n, double re, double im, hipStream_t s);
+void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s);
 // psi[i*nrhs + q] *= scale[q]
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s);
 

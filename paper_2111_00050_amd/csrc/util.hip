@@ -84,6 +84,62 @@ __global__ void dot_re_kernel(const double* g, const double* z, long long total,
     if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
 }
 
+// One Chebyshev term (n complex entries): next = alpha h + beta x + gamma prev
+// (prev may be NULL when gamma == 0; next may alias prev), then
+// acc = (init ? c0 x : acc) + c next, with complex c0, c.
+__global__ void cheb_term_kernel(const double* h, const double* x, const double* prev, double* next, double* acc,
+                                 long long n, double alpha, double beta, double gamma, double c_re, double c_im,
+                                 int init, double c0_re, double c0_im) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double xr = x[2 * i], xi = x[2 * i + 1];
+        double nr = fma(alpha, h[2 * i], beta * xr), ni = fma(alpha, h[2 * i + 1], beta * xi);
+        if (prev) {
+            nr = fma(gamma, prev[2 * i], nr);
+            ni = fma(gamma, prev[2 * i + 1], ni);
+        }
+        double ar, ai;
+        if (init) {
+            ar = c0_re * xr - c0_im * xi;
+            ai = c0_re * xi + c0_im * xr;
+        } else {
+            ar = acc[2 * i];
+            ai = acc[2 * i + 1];
+        }
+        acc[2 * i] = ar + (c_re * nr - c_im * ni);
+        acc[2 * i + 1] = ai + (c_re * ni + c_im * nr);
+        next[2 * i] = nr;
+        next[2 * i + 1] = ni;
+    }
+}
+
+// out = (re + i im) * in   (n complex entries; out may alias in)
+__global__ void cscale_kernel(double* out, const double* in, long long n, double re, double im) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double xr = in[2 * i], xi = in[2 * i + 1];
+        out[2 * i] = re * xr - im * xi;
+        out[2 * i + 1] = re * xi + im * xr;
+    }
+}
+
+// Deterministic start vector: entry i from the SplitMix64 finaliser of (seed, i),
+// real and imaginary parts uniform in [-1, 1).
+__device__ __forceinline__ unsigned long long splitmix64(unsigned long long z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__global__ void hash_fill_kernel(double* x, long long n, unsigned long long seed) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const unsigned long long r = splitmix64(seed ^ (0x632BE59BD9B4E019ull * (unsigned long long)(i + 1)));
+        x[2 * i] = (double)(r >> 11) * 0x1.0p-52 - 1.0;
+        x[2 * i + 1] = (double)(splitmix64(r) >> 11) * 0x1.0p-52 - 1.0;
+    }
+}
+
 static unsigned grid_for(long long n) {
     long long b = (n + 255) / 256;
     if (b > 65536) b = 65536;
@@ -115,6 +171,19 @@ int launch_dot_re(const double* g, const double* z, long long total, int nrhs, i
     const int G = 1024;
     hipLaunchKernelGGL(dot_re_kernel, dim3(G), dim3(256), 0, s, g, z, total, nrhs, rhs, partial);
     return G;
+}
+void launch_cheb_term(const double* h, const double* x, const double* prev, double* next, double* acc, long long n,
+                      double alpha, double beta, double gamma, double c_re, double c_im, int init, double c0_re,
+                      double c0_im, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(cheb_term_kernel, dim3(grid_for(n)), dim3(256), 0, s, h, x, prev, next, acc, n, alpha, beta,
+                           gamma, c_re, c_im, init, c0_re, c0_im);
+}
+void launch_cscale(double* out, const double* in, long long n, double re, double im, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cscale_kernel, dim3(grid_for(n)), dim3(256), 0, s, out, in, n, re, im);
+}
+void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(hash_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, seed);
 }
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s) {
     if (total > 0)

@@ -91,3 +91,23 @@ def test_derive_host_only_against_oracle():
         # eigenvector up to a phase
         ph = np.vdot(o["xi"], g["xi"])
         assert abs(abs(ph) - 1) < 1e-10
+
+
+def test_chebyshev_coefficients_host_only():
+    """Series coefficients of exp(-i x T): c_0 = J_0(x), c_k = 2 (-i)^k J_k(x)
+    (scipy's Bessel functions as the reference) and the oracle's term count."""
+    import paper_2111_00050_amd as fh
+    from scipy.special import jv
+
+    from oracle import evolve
+
+    for x, tol in ((0.05, 1e-14), (3.7, 1e-14), (41.0, 1e-12)):
+        c = fh.chebyshev_coefficients(x, tol)
+        assert len(c) == evolve.chebyshev_terms(x, tol)
+        k = np.arange(len(c))
+        want = np.where(k == 0, 1.0, 2.0) * (-1j) ** k * jv(k, x)
+        np.testing.assert_allclose(c, want, rtol=0, atol=1e-14)
+    with pytest.raises(ValueError):
+        fh.chebyshev_coefficients(-1.0)
+    with pytest.raises(ValueError):
+        fh.chebyshev_coefficients(5000.0)

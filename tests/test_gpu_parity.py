@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import Oracle, derived, evolve, states
+from oracle import Oracle, dense, derived, evolve, states
 
 pytestmark = pytest.mark.gpu
 
@@ -476,3 +476,54 @@ def test_tangent_two_rhs():
         one = fh.tangent_rk4(model, b, fh.init_coherent(b, al[q]), dt, nsteps, fh.FH_J_Q)
         assert abs(both["J"][q] - one["J"][0]) <= 1e-14
         assert abs(both["dLambda"][q] - one["dLambda"][0]) <= 1e-12 * max(1.0, abs(one["dLambda"][0]))
+
+
+# ---------------------------------------------------- Chebyshev propagator ---
+def test_chebyshev_vs_oracle_and_exponential():
+    """Large steps (|E| dt far past RK4's limit): equal to the oracle's series
+    and to the dense exponential."""
+    w = W.tiny_number()
+    orc, model, b = _pair(w.M, w.sectors, w.omega, w.Lambda, w.V)
+    H = dense.dense_h(orc)
+    E = np.linalg.eigvalsh(H)
+    emin, emax = E.min() - 0.5, E.max() + 0.5
+    dt, n = 0.7, 5
+    psi = fh.init_number(b, w.init_params)
+    res = fh.evolve_chebyshev(model, b, psi, dt, n, emin, emax, every=1)
+    psi0 = states.number_state(orc, w.init_params)
+    ref, recs = evolve.chebyshev(orc, psi0, dt, n, emin, emax, every=1, observe=lambda s, t, p: orc.moments(p))
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-12
+    assert np.linalg.norm(psi.cpu().numpy() - dense.expm_evolve(H, psi0, n * dt)) <= 1e-11
+    _check_records(w.M, res, recs)
+
+
+@pytest.mark.parametrize("flags", [0, fh.FH_PER_SECTOR])
+def test_chebyshev_multisector_vs_rk4(flags):
+    """Coherent state over many sectors: a few Chebyshev steps agree with many
+    small RK4 steps to the RK4 error; bounds from the power iteration."""
+    M, Lam = 4, 0.3
+    alpha = W.coherent_amplitudes(13, M, 2.0)
+    sectors = W.all_sectors(M, 12)
+    orc, model, b = _pair(M, sectors, W.omega_quadratic(M), Lam, W.V_longrange(M))
+    psi_c = fh.init_coherent(b, alpha)
+    fh.evolve_chebyshev(model, b, psi_c, 0.1, 3, flags=flags)
+    psi_r = fh.init_coherent(b, alpha)
+    fh.evolve_rk4(model, b, psi_r, 1e-4, 3000)
+    assert _rel(psi_c.cpu().numpy(), psi_r.cpu().numpy()) <= 1e-9
+
+
+def test_spectral_radius_power_iteration():
+    w = W.tiny_number()
+    orc, model, b = _pair(w.M, w.sectors, w.omega, w.Lambda, w.V)
+    rho = np.abs(np.linalg.eigvalsh(dense.dense_h(orc))).max()
+    est = fh.spectral_radius(model, b, iters=300)
+    assert 0.95 * rho <= est <= rho * (1 + 1e-12)
+
+
+def test_chebyshev_rejects_a_too_small_interval():
+    w = W.tiny_number()
+    orc, model, b = _pair(w.M, w.sectors, w.omega, w.Lambda, w.V)
+    rho = np.abs(np.linalg.eigvalsh(dense.dense_h(orc))).max()
+    psi = fh.init_number(b, w.init_params)
+    with pytest.raises(fh.FockError):
+        fh.evolve_chebyshev(model, b, psi, 2.0, 20, -0.2 * rho, 0.2 * rho)
