@@ -527,3 +527,61 @@ def test_chebyshev_rejects_a_too_small_interval():
     psi = fh.init_number(b, w.init_params)
     with pytest.raises(fh.FockError):
         fh.evolve_chebyshev(model, b, psi, 2.0, 20, -0.2 * rho, 0.2 * rho)
+
+
+# ------------------------------------------------------------ edge cases ---
+def test_empty_and_single_state_sectors():
+    """Sectors with no states (N = 0, P != 0) and with one state sit in the
+    basis without effect: evolution and moments match the oracle."""
+    M = 4
+    sectors = [(0, 1), (0, 0), (1, 3), (5, 2), (4, 0), (3, 1)]
+    omega, V = _model("sym", M, 5)
+    orc, model, b = _pair(M, sectors, omega, 0.4, V)
+    assert b.dims[0] == 0 and b.dims[1] == 1
+    x = W.random_psi(orc.total, 21)
+    assert _rel(fh.apply_h(model, b, torch.from_numpy(x).cuda()).cpu().numpy(), orc.apply_h(x)) <= 1e-13
+    psi = torch.from_numpy(x).cuda()
+    res = fh.evolve_rk4(model, b, psi, 1e-2, 30, every=10)
+    ref, recs = _oracle_run(orc, x, 1e-2, 30, 10)
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-10
+    _check_records(M, res, recs)
+
+
+def test_vacuum_only_basis():
+    """The one-state basis {|0>}: H|0> = 0 and every moment but the norm vanishes."""
+    M = 3
+    model, b = fh.Model(M, W.omega_quadratic(M), 0.5, W.V_contact(M)), fh.Basis(M, [(0, 0)])
+    psi = torch.tensor([0.6 - 0.8j], dtype=torch.complex128, device="cuda")
+    assert torch.count_nonzero(fh.apply_h(model, b, psi)) == 0
+    res = fh.evolve_rk4(model, b, psi, 0.1, 5, every=5)
+    n2, a, Mij, Akl = fh.unpack_moments(M, res.records[-1, 0])
+    assert abs(n2 - 1.0) <= 1e-15 and not a.any() and not Mij.any() and not Akl.any()
+
+
+def test_classical_edge_arguments():
+    M = 3
+    model = fh.Model(M, W.omega_quadratic(M), 0.2, W.V_contact(M))
+    a0 = W.coherent_amplitudes(3, M, 1.0)
+    aT, traj = fh.classical_rk4(model, a0, 1e-2, 0, every=1)  # zero steps: only the initial record
+    assert traj.shape == (1, 1, M) and np.array_equal(traj.cpu().numpy()[0, 0], a0)
+    assert np.array_equal(aT.cpu().numpy()[0], a0)
+    aT2, none = fh.classical_rk4(model, a0, 1e-2, 10)
+    assert none is None and aT2.shape == (1, M)
+
+
+def test_error_returns_are_exceptions():
+    """Invalid calls come back as FockError with the library's message and
+    launch nothing."""
+    M = 3
+    model, b = fh.Model(M, W.omega_quadratic(M), 0.2, W.V_contact(M)), fh.Basis(M, W.all_sectors(M, 4))
+    x = torch.from_numpy(W.random_psi(b.total, 1, nrhs=3)).cuda()
+    with pytest.raises(fh.FockError, match="nrhs"):
+        fh.apply_h(model, b, x)
+    y = torch.from_numpy(W.random_psi(b.total, 1)).cuda()
+    with pytest.raises(fh.FockError, match="alias"):
+        fh.apply_h(model, b, y, out=y)
+    other = fh.Model(M + 1, W.omega_quadratic(M + 1), 0.2, W.V_contact(M + 1))
+    with pytest.raises(fh.FockError, match="disagree"):
+        fh.apply_h(other, b, y)
+    with pytest.raises(fh.FockError, match="emin < emax"):
+        fh.evolve_chebyshev(model, b, y, 0.1, 1, 1.0, -1.0)
