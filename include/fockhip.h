@@ -153,6 +153,20 @@ typedef struct {
 fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c64* Mij, const fh_c64* Akl,
                     fh_obs_scalars* s, fh_c64* xi, double* vminus_mode);
 
+/* ------------------------------------------------------------ breaktimes --
+ * First time a sampled observable reaches a level: the quantum breaktimes
+ * Q(t) = 0.15 (Sec. IV.C), 1 - lambda_p/n_tot = 0.1 (Sec. IV.D) and the
+ * squeezing onset V_-(t) = 0.8 (Sec. II.E, Sec. IV.E).  Host only.
+ * t[n], y[n]: host arrays, t strictly increasing.  direction = +1 looks for
+ * y rising to the level (first y[i] >= level), -1 for y falling to it (first
+ * y[i] <= level).  *out = t[i] if i is the first sample or follows a non-finite
+ * one, else the linear interpolation between samples i-1 and i; NaN when the
+ * level is never reached.  Non-finite samples are skipped.  FH_EINVAL for a
+ * null pointer, n < 0, direction not +-1, a non-finite level or t not strictly
+ * increasing (then *out = NaN). */
+fh_status fh_first_crossing(const double* t, const double* y, long long n, double level, int direction,
+                            double* out);
+
 /* ----------------------------------------------------------------- evolve --
  * nsteps classical RK4 steps of dt on d psi/dt = -i H psi, in place on psi
  * (device, total*nrhs).  work: device scratch of 3*total*nrhs fh_c64.

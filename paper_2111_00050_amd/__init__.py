@@ -70,6 +70,7 @@ SIGNATURES = {
     "fh_apply_h": (_I, [_P, _P, _I, _P, _P, _P]),
     "fh_moments": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P]),
+    "fh_first_crossing": (_I, [_P, _P, _I64, _D, _I, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_evolve_taylor2": (_I, [_P, _P, _I, _P, _P, _D, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_classical_rk4": (_I, [_P, _I, _P, _D, _I64, _I64, _P, _P]),
@@ -338,6 +339,45 @@ def derive(M, norm2, a, Mij, Akl):
     out.update(a=a / norm2 if norm2 else a, M=Mij / norm2 if norm2 else Mij, A=Akl / norm2 if norm2 else Akl,
                xi=xi, vminus_mode=vm)
     return out
+
+
+def first_crossing(t, y, level, direction=1):
+    """First time the sampled y(t) reaches `level` (direction +1 rising, -1
+    falling), linearly interpolated; NaN if it never does (fh_first_crossing)."""
+    t = np.ascontiguousarray(t, np.float64)
+    y = np.ascontiguousarray(y, np.float64)
+    if t.shape != y.shape or t.ndim != 1:
+        raise ValueError("t and y must be 1-D arrays of equal length")
+    out = np.zeros(1)
+    _check(_lib.fh_first_crossing(_np_ptr(t), _np_ptr(y), len(t), float(level), int(direction), _np_ptr(out)))
+    return float(out[0])
+
+
+BREAK_Q = 0.15      # Q(t_br) (Sec. IV.C)
+BREAK_PO = 0.1      # 1 - lambda_p / n_tot at t_br (Sec. IV.D)
+ONSET_VMINUS = 0.8  # V_-(t_sqz) (Sec. II.E)
+
+
+def observable_series(M, res, dt, rhs=0):
+    """Derived observables of every record of an evolve result: dict of arrays
+    t, n_tot, Q, lambda_p, po_deficit, vminus."""
+    keys = ("n_tot", "Q", "lambda_p", "po_deficit", "vminus")
+    out = {k: np.empty(len(res.records)) for k in keys}
+    for r, rec in enumerate(res.records[:, rhs]):
+        d = derive(M, *unpack_moments(M, rec))
+        for k in keys:
+            out[k][r] = d[k]
+    out["t"] = np.asarray(res.steps, np.float64) * dt
+    return out
+
+
+def breaktimes(series, q=BREAK_Q, po=BREAK_PO, vminus=ONSET_VMINUS):
+    """The three breaktimes of the paper from an observable series: Q rising to
+    0.15, the PO deficit rising to 0.1, V_- falling to 0.8 (NaN if not reached)."""
+    t = series["t"]
+    return {"t_Q": first_crossing(t, series["Q"], q, 1),
+            "t_PO": first_crossing(t, series["po_deficit"], po, 1),
+            "t_sqz": first_crossing(t, series["vminus"], vminus, -1)}
 
 
 # ---------------------------------------------------------------- evolve ---

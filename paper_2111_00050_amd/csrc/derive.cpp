@@ -133,3 +133,26 @@ extern "C" fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c6
     if (!std::isfinite(ntot) || !std::isfinite(lam)) return FH_ESTATE;
     return FH_OK;
 }
+
+extern "C" fh_status fh_first_crossing(const double* t, const double* y, long long n, double level, int direction,
+                                       double* out) {
+    if (!out) return FH_EINVAL;
+    *out = std::numeric_limits<double>::quiet_NaN();
+    if (n < 0 || (n > 0 && (!t || !y)) || (direction != 1 && direction != -1) || !std::isfinite(level))
+        return FH_EINVAL;
+    for (long long i = 1; i < n; ++i)
+        if (!(t[i] > t[i - 1])) return FH_EINVAL;
+    // past(v): the sample lies at or beyond the level in the crossing direction
+    auto past = [&](double v) { return direction > 0 ? v >= level : v <= level; };
+    for (long long i = 0; i < n; ++i) {
+        if (!std::isfinite(y[i]) || !past(y[i])) continue;
+        if (i == 0 || !std::isfinite(y[i - 1])) {
+            *out = t[i];
+        } else {
+            const double f = (level - y[i - 1]) / (y[i] - y[i - 1]);
+            *out = t[i - 1] + f * (t[i] - t[i - 1]);
+        }
+        return FH_OK;
+    }
+    return FH_OK;
+}

@@ -111,3 +111,31 @@ def test_chebyshev_coefficients_host_only():
         fh.chebyshev_coefficients(-1.0)
     with pytest.raises(ValueError):
         fh.chebyshev_coefficients(5000.0)
+
+
+def test_first_crossing_host_only():
+    """Breaktime extraction: exact on piecewise-linear data, within the linear
+    interpolation bound h^2 max|y''| / 8 on a smooth curve, NaN when the level
+    is never reached, errors on bad arguments."""
+    import paper_2111_00050_amd as fh
+
+    t = np.linspace(0.0, 2.0, 21)
+    assert abs(fh.first_crossing(t, 3.0 * t - 1.0, 2.0) - 1.0) <= 1e-15
+    assert abs(fh.first_crossing(t, 1.0 - 0.25 * t, 0.8, -1) - 0.8) <= 1e-15
+    h = t[1] - t[0]
+    got = fh.first_crossing(t, t ** 2, 0.15)
+    # the chord of a convex curve lies above it: the crossing comes early
+    assert 0.0 < np.sqrt(0.15) - got <= h * h * 2.0 / 8.0 / (2.0 * (np.sqrt(0.15) - h))
+    assert np.isnan(fh.first_crossing(t, t ** 2, 9.0))
+    assert fh.first_crossing(t, t + 1.0, 0.5) == 0.0          # already past at the first sample
+    y = t ** 2
+    y[3] = np.nan
+    assert abs(fh.first_crossing(t, y, y[2] + 1e-3) - t[4]) <= 1e-15  # bracket broken by NaN
+    assert np.isnan(fh.first_crossing(np.zeros(0), np.zeros(0), 1.0))
+    with pytest.raises(fh.FockError):
+        fh.first_crossing(t[::-1].copy(), y, 0.5)
+    with pytest.raises(fh.FockError):
+        fh.first_crossing(t, y, 0.5, direction=0)
+    s = {"t": t, "Q": 0.1 * t, "po_deficit": 0.05 * t, "vminus": 1.0 - 0.1 * t}
+    bt = fh.breaktimes(s)
+    assert abs(bt["t_Q"] - 1.5) < 1e-14 and abs(bt["t_PO"] - 2.0) < 1e-14 and abs(bt["t_sqz"] - 2.0) < 1e-14

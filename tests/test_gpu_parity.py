@@ -585,3 +585,81 @@ def test_error_returns_are_exceptions():
         fh.apply_h(other, b, y)
     with pytest.raises(fh.FockError, match="emin < emax"):
         fh.evolve_chebyshev(model, b, y, 0.1, 1, 1.0, -1.0)
+
+
+# ---------------------------------------------- exact momentum (Sec. IV.A) ---
+def _exact_oracle(w, sectors_exact):
+    pmod = max(N for N, _ in sectors_exact) * (w.M - 1) + 1
+    return Oracle(w.M, pmod, w.omega, w.Lambda, w.V, sectors_exact)
+
+
+def _rows_of(b, orc):
+    """GPU basis row of every oracle (exact-sector) state, matched by occupations."""
+    occ = b.occupations().cpu().numpy()
+    row = {o.tobytes(): r for r, o in enumerate(occ)}
+    return np.array([row[o.tobytes()] for o in orc.all_occupations()], np.int64)
+
+
+@pytest.mark.parametrize("inter", ["longrange", "contact+", "contact-"])
+def test_paper_number_state_exact_momentum(inter):
+    """|0, 2r, 2r, r, 0> (r = 2) with the paper's exactly conserving
+    interactions: the periodic sector holding it evolves, on the GPU, exactly as
+    the oracle's exact sector (Sigma j n_j = 18) and every other state stays 0."""
+    w = W.paper_problem("number", inter, 2)
+    N, P = w.sectors[0]
+    orc = _exact_oracle(w, [(N, w.meta["P_exact"])])
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    rows = _rows_of(b, orc)
+    assert b.total > orc.total
+    psi = fh.init_number(b, w.init_params)
+    dt, nsteps, every = 2e-3, 400, 100
+    res = fh.evolve_rk4(model, b, psi, dt, nsteps, every=every)
+    ref, recs = _oracle_run(orc, states.number_state(orc, w.init_params), dt, nsteps, every)
+    got = psi.cpu().numpy()
+    assert np.linalg.norm(got[rows] - ref) <= 1e-10
+    rest = np.ones(b.total, bool)
+    rest[rows] = False
+    assert np.all(got[rest] == 0)
+    _check_records(w.M, res, recs)
+
+
+@pytest.mark.parametrize("init,inter", [("coherent", "longrange"), ("coherent", "contact-"),
+                                        ("fieldnumber", "longrange")])
+def test_paper_superpositions_exact_momentum(init, inter):
+    """Coherent and field-number states of the paper's test problems (r = 1):
+    all periodic sectors together equal all exact sectors; amplitudes and
+    observables on the GPU match the oracle run in the exact basis, and so do
+    the breaktimes Q = 0.15, 1 - lambda_p/n_tot = 0.1 extracted from both."""
+    w = W.paper_problem(init, inter, 1)
+    z = w.init_params[0]
+    if init == "coherent":
+        Nmax = 10
+        sectors = W.all_sectors(w.M, Nmax)
+        exact = [(N, P) for N in range(Nmax + 1) for P in range(N * (w.M - 1) + 1)]
+    else:
+        sectors = w.sectors
+        N = sectors[0][0]
+        exact = [(N, P) for P in range(N * (w.M - 1) + 1)]
+    orc = _exact_oracle(w, exact)
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, sectors)
+    rows = _rows_of(b, orc)
+    assert sorted(rows.tolist()) == list(range(b.total))
+    if init == "coherent":
+        psi, ref0 = fh.init_coherent(b, z), states.coherent_state(orc, z)
+    else:
+        psi, ref0 = fh.init_fieldnumber(b, z), states.fieldnumber_state(orc, z)
+    assert _rel(psi.cpu().numpy()[rows], ref0) <= 1e-13
+    dt, nsteps, every = 1e-2, 200, 5
+    res = fh.evolve_rk4(model, b, psi, dt, nsteps, every=every)
+    ref, recs = evolve.rk4(orc, ref0, dt, nsteps, every=every, observe=lambda s, t, p: orc.moments(p))
+    assert np.linalg.norm(psi.cpu().numpy()[rows] - ref) <= 1e-10
+    _check_records(w.M, res, recs)
+    ser = fh.observable_series(w.M, res, dt)
+    t = np.arange(len(recs)) * every * dt
+    want = [derived.derive(*r) for r in recs]
+    for key, level in (("Q", fh.BREAK_Q), ("po_deficit", fh.BREAK_PO)):
+        ref_t = fh.first_crossing(t, np.array([d[key] for d in want]), level)
+        got_t = fh.first_crossing(ser["t"], ser[key], level)
+        if init == "coherent":
+            assert 0.0 < ref_t < nsteps * dt
+        assert abs(got_t - ref_t) <= 1e-8 or (np.isnan(got_t) and np.isnan(ref_t))

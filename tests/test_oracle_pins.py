@@ -496,3 +496,119 @@ def test_x2_chebyshev_free_phases(oracle_lib):
     E = o.all_occupations() @ om
     psi, _ = evolve.chebyshev(o, psi0, dt, n, -1.0, E.max() + 1.0)
     np.testing.assert_allclose(psi, psi0 * np.exp(-1j * E * n * dt), rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------------ E1-E2 --
+def _brute_two_body(occs, quads):
+    """<m| sum_q c_q a_a^+ a_b^+ a_c a_d |n> by explicit ladder operators on
+    occupation tuples (a^+|n> = sqrt(n+1)|n+1>, a|n> = sqrt(n)|n-1>)."""
+    index = {tuple(int(x) for x in o): r for r, o in enumerate(occs)}
+    H = np.zeros((len(occs), len(occs)))
+    for col, o in enumerate(occs):
+        for (a, b, c, d), coef in quads:
+            v = [int(x) for x in o]
+            amp = coef
+            for mode, create in ((d, False), (c, False), (b, True), (a, True)):
+                if create:
+                    v[mode] += 1
+                    amp *= math.sqrt(v[mode])
+                else:
+                    amp *= math.sqrt(v[mode])
+                    v[mode] -= 1
+                    if v[mode] < 0:
+                        amp = 0.0
+                        break
+            if amp != 0.0:
+                H[index[tuple(v)], col] += amp
+    return H
+
+
+@pytest.mark.parametrize("N", [3, 5])
+def test_e1_exact_interactions_are_eq_lambda(oracle_lib, N):
+    """Sec. II.A, Eq. (Ham) with Eq. (Lambda) on the grid p_j = j: the
+    interaction (1/2) sum Lambda^{ij}_{kl} a_k^+ a_l^+ a_i a_j, each transfer term
+    C / (2 (p_k - p_i)^2) kept only where it is finite, built here term by term
+    with ladder operators, equals the oracle's H for V_longrange_exact (Lambda = C)
+    plus V_contact_exact (Lambda = Lambda_0), in every exact momentum sector."""
+    M, C, L0 = 5, -0.3, 0.7
+    quads = []
+    for i, j, k, l in itertools.product(range(M), repeat=4):
+        if i + j != k + l:
+            continue
+        lam = L0 + sum(C / (2.0 * (k - x) ** 2) for x in (i, j) if x != k)
+        quads.append(((k, l, i, j), 0.5 * lam))
+    pmod = N * (M - 1) + 1
+    for P in range(0, N * (M - 1) + 1, 3):
+        oc = Oracle(M, pmod, np.zeros(M), C, W.V_longrange_exact(M), [(N, P)])
+        oo = Oracle(M, pmod, np.zeros(M), L0, W.V_contact_exact(M), [(N, P)])
+        want = _brute_two_body(oc.occupations(0), quads)
+        got = dense.dense_h(oc) + dense.dense_h(oo)
+        assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max())
+
+
+@pytest.mark.parametrize("inter", ["longrange", "contact+"])
+def test_e2_periodic_sector_embeds_exact_sectors(oracle_lib, inter):
+    """With an exactly conserving V, the periodic sector (N, P mod M) is the union
+    of the exact sectors P' = P (mod M), 0 <= P' <= N (M-1), and H does not couple
+    them: permuted to exact order, the periodic H is block diagonal with the exact
+    sectors' H as blocks (Sec. III.B; exact Sigma j n_j)."""
+    w = W.paper_problem("number", inter, 1)
+    M, N = w.M, 6
+    pmod = N * (M - 1) + 1
+    for P in range(M):
+        per = Oracle(M, M, w.omega, w.Lambda, w.V, [(N, P)])
+        exact_secs = [(N, q) for q in range(P, N * (M - 1) + 1, M)]
+        ex = Oracle(M, pmod, w.omega, w.Lambda, w.V, exact_secs)
+        row = {tuple(o): r for r, o in enumerate(per.occupations(0))}
+        perm = np.array([row[tuple(o)] for o in ex.all_occupations()])
+        assert sorted(perm.tolist()) == list(range(per.total))
+        Hp = dense.dense_h(per)[np.ix_(perm, perm)]
+        He = dense.dense_h(ex)
+        assert np.abs(Hp - He).max() <= 1e-13 * np.abs(He).max()
+
+
+# ------------------------------------------------------------------ S1-S2 --
+def _bajer(tau, n):
+    s = math.sqrt(1.0 + 4.0 * tau * tau)
+    return 1 - 4 * tau * s + 8 * tau ** 2 + 8 * tau ** 3 * (5 + 12 * tau ** 2) / (n * s) - 16 * tau ** 4 / n
+
+
+def _kerr_vminus(n, taus, Lam=0.01):
+    """V_- of a single-mode Kerr coherent state (where the single-field picture
+    of Sec. II.E is exact) at the given tau = n_tot |chi| t, by the oracle's RK4."""
+    o = Oracle(1, 1, np.zeros(1), Lam, np.ones((1, 1, 1, 1)), [(N, 0) for N in range(W.poisson_cut(n) + 1)])
+    z = np.array([math.sqrt(n) * np.exp(0.4j)])
+    psi = states.coherent_state(o, z)
+    chi = 0.5 * Lam * n        # n_tot |chi| = (1/n) (Lambda/2) |z|^4
+    out, t, nsub = [], 0.0, 400
+    for tau in taus:
+        h = (tau / chi - t) / nsub
+        psi, _ = evolve.rk4(o, psi, h, nsub)
+        t = tau / chi
+        out.append(derived.observe(o, psi)["vminus"])
+    return np.array(out)
+
+
+def test_s1_squeezing_follows_the_large_n_approximation(oracle_lib):
+    """Sec. II.E, Eq. (VminusBajer): for n_tot > 20 the approximation is accurate;
+    its error is O(1/n_tot^2) (a 2.5x larger n_tot shrinks it about 6x)."""
+    taus = [0.01, 0.05, 0.1, 0.3]
+    v20 = _kerr_vminus(20.0, taus)
+    v50 = _kerr_vminus(50.0, taus)
+    e20 = np.abs(v20 - [_bajer(t, 20.0) for t in taus])
+    e50 = np.abs(v50 - [_bajer(t, 50.0) for t in taus])
+    assert np.all(e50[:3] <= 1e-6) and e50[3] <= 3e-4
+    assert 4.0 <= e20[3] / e50[3] <= 9.0
+
+
+def test_s2_early_time_squeezing_slope(oracle_lib):
+    """Sec. II.E: V_- = 1 - 4 tau + O(tau^2) at early times; the onset
+    V_- = 0.8 lies near tau = 0.05 (t_sqz = 0.05 / (n_tot |chi|))."""
+    taus = [1e-3, 2e-3]
+    v = _kerr_vminus(50.0, taus)
+    slope = (1.0 - v) / (4.0 * np.array(taus))
+    # 1 - slope = O(tau): halving tau halves the gap
+    assert abs(1.0 - slope[0]) <= 2e-3
+    assert 1.7 <= (1.0 - slope[1]) / (1.0 - slope[0]) <= 2.3
+    a, b = _kerr_vminus(50.0, [0.05, 0.06])
+    assert a > 0.8 > b

@@ -86,6 +86,32 @@ def V_random(M: int, seed: int, pmod: int | None = None) -> np.ndarray:
     return rng.uniform(-1.0, 1.0, size=(M, M, M, M)) * cons
 
 
+# ------------------------------------------- exact momentum (paper grid) ---
+# The paper's own model (Sec. II.A, Eq. Lambda; Sec. IV.A): mode j carries
+# momentum p_j = j on a non-periodic grid and the interaction conserves
+# sum_j j n_j exactly (i + j == k + l).  Such a V also conserves it modulo M,
+# so the periodic sectors (N, P mod M) of the GPU path are unions of exact
+# sectors that the dynamics never couples.
+def _exact(M: int):
+    i, j, k, l = np.meshgrid(*(np.arange(M),) * 4, indexing="ij")
+    return (i + j) == (k + l), i, k
+
+
+def V_contact_exact(M: int) -> np.ndarray:
+    cons, _, _ = _exact(M)
+    return cons.astype(np.float64)
+
+
+def V_longrange_exact(M: int) -> np.ndarray:
+    """1/(p_k - p_i)^2 per ordered term, p_j = j, zero transfer removed."""
+    cons, i, k = _exact(M)
+    q = (k - i).astype(np.float64)
+    V = np.zeros((M, M, M, M))
+    nz = cons & (q != 0)
+    V[nz] = 1.0 / q[nz] ** 2
+    return V
+
+
 # ---------------------------------------------------------------- inputs ---
 def momentum(occ, pmod: int) -> int:
     occ = np.asarray(occ)
@@ -224,3 +250,37 @@ def fieldnumber_draws(ndraws: int = 16, N: int = 30) -> Workload:
     z = phase_draws(n, range(500, 500 + ndraws))
     return Workload(f"field-number draws M=10 N={N} x{ndraws}", M, omega_linear(M), V_contact(M), 0.01,
                     [(N, P) for P in range(M)], 2e-4, 2000, 50, "fieldnumber", z)
+
+
+def paper_problem(init: str, interaction: str, r: int, seed: int = 7) -> Workload:
+    """The test problems of Sec. IV.A on M = 5 modes with exact momentum:
+    initial state |0, 2r, 2r, r, 0> (init "number") or z = (0, sqrt(2r) e^{i t1},
+    sqrt(2r) e^{i t2}, sqrt(r) e^{i t3}, 0) (init "coherent" / "fieldnumber",
+    phases from the seed); interaction "longrange": w_j = j^2/2, C = -0.1/r
+    (Lambda = C with V = V_longrange_exact), or "contact+" / "contact-":
+    w_j = j/r, Lambda_0 = +-0.1/r (Lambda = Lambda_0 with V = V_contact_exact).
+    Sectors: periodic (N, P mod 5) covering the state (see above)."""
+    M = 5
+    j = np.arange(M, dtype=np.float64)
+    if interaction == "longrange":
+        omega, V, Lam = 0.5 * j ** 2, V_longrange_exact(M), -0.1 / r
+    elif interaction in ("contact+", "contact-"):
+        omega, V = j / r, V_contact_exact(M)
+        Lam = (0.1 if interaction == "contact+" else -0.1) / r
+    else:
+        raise ValueError(interaction)
+    n = np.array([0, 2 * r, 2 * r, r, 0])
+    N = int(n.sum())
+    if init == "number":
+        return Workload(f"paper number state r={r} {interaction}", M, omega, V, Lam,
+                        [(N, momentum(n, M))], 1e-3, 0, 0, "number", n, meta={"P_exact": int(j @ n)})
+    th = np.random.default_rng(seed).uniform(0.0, 2.0 * np.pi, size=3)
+    z = np.array([0.0, np.sqrt(2 * r) * np.exp(1j * th[0]), np.sqrt(2 * r) * np.exp(1j * th[1]),
+                  np.sqrt(r) * np.exp(1j * th[2]), 0.0])
+    if init == "fieldnumber":
+        return Workload(f"paper field-number state r={r} {interaction}", M, omega, V, Lam,
+                        [(N, P) for P in range(M)], 1e-3, 0, 0, "fieldnumber", z[None, :])
+    if init == "coherent":
+        return Workload(f"paper coherent state r={r} {interaction}", M, omega, V, Lam,
+                        all_sectors(M, poisson_cut(float(N))), 1e-3, 0, 0, "coherent", z[None, :])
+    raise ValueError(init)
