@@ -257,10 +257,17 @@ def test_p10_long_range_interaction_energy(oracle_lib):
             z = np.array([0, math.sqrt(2 * r) * np.exp(1j * th[0]), math.sqrt(2 * r) * np.exp(1j * th[1]),
                           math.sqrt(r) * np.exp(1j * th[2]), 0])
             ntot = 5 * r
-            e = 0.5 * C * np.einsum("ijkl,i,j,k,l->", V, z.conj(), z.conj(), z, z)
             want = abs(0.13 + 0.08 * math.sqrt(2) * math.cos(th[0] + th[2] - 2 * th[1]))
-            assert abs(abs(e) / ntot - want) < 1e-12
+            # periodic minimal-image and exact (p_j = j) transfers agree on modes 1..3
+            for VV in (V, W.V_longrange_exact(M)):
+                e = 0.5 * C * np.einsum("ijkl,i,j,k,l->", VV, z.conj(), z.conj(), z, z)
+                assert abs(abs(e) / ntot - want) < 1e-12
     assert 0.13 + 0.08 * math.sqrt(2) >= 0.242
+    # the default phases of the workload generator reproduce the printed value
+    w = W.paper_problem("coherent", "longrange", 2)
+    z = w.init_params[0]
+    e = 0.5 * w.Lambda * np.einsum("ijkl,i,j,k,l->", w.V, z.conj(), z.conj(), z, z)
+    assert round(abs(e) / 10.0, 3) == 0.242
     # the oracle's H reproduces the normal-ordered energy on the truncated state (r = 1)
     r, C = 1.0, -0.1
     th = np.array([0.3, 1.7, 0.2])

@@ -1,0 +1,112 @@
+"""Breaktimes of the paper's test problems as the occupation grows (Sec. IV.C-E).
+
+For each average occupation r the chosen problem (Sec. IV.A: number, coherent or
+field-number initial state; long-range or contact interactions, exact momentum)
+is evolved on the GPU with the Chebyshev propagator in record intervals of
+--interval, until Q has reached 0.15, 1 - lambda_p/n_tot has reached 0.1 and V_-
+has fallen to 0.8 (or --t-max).  Coherent states keep the sectors N <= N_max with
+the smallest N_max whose Poisson weight is >= 0.999 (Sec. IV.A).  One JSON line
+per r: sizes, the three breaktimes, the squeezing-onset prediction
+t_sqz = 0.05 n_tot / |sum (1/2) Lambda z* z* z z| (Sec. II.E) and the wall time.
+
+    python workloads/breaktime_sweep.py --problem coherent-longrange --r 1 2 4 8
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+import workloads as W  # noqa: E402
+
+
+def poisson_nmax(mean: float, weight: float = 0.999) -> int:
+    """Smallest N with P(Poisson(mean) <= N) >= weight."""
+    p = math.exp(-mean)
+    acc, N = p, 0
+    while acc < weight:
+        N += 1
+        p *= mean / N
+        acc += p
+    return N
+
+
+def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float):
+    import torch
+
+    import paper_2111_00050_amd as fh
+
+    init, inter = problem.split("-", 1)
+    w = W.paper_problem(init, inter, r, seed=seed)
+    if init == "coherent":
+        z = w.init_params[0]
+        n = float(np.sum(np.abs(z) ** 2))
+        sectors = W.all_sectors(w.M, poisson_nmax(n))
+    else:
+        sectors = w.sectors
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, sectors)
+    if init == "number":
+        psi = fh.init_number(b, w.init_params)
+        zc = np.sqrt(w.init_params.astype(np.float64))
+    elif init == "coherent":
+        psi, zc = fh.init_coherent(b, w.init_params[0]), w.init_params[0]
+    else:
+        psi, zc = fh.init_fieldnumber(b, w.init_params[0]), w.init_params[0]
+    n_tot = float(np.sum(np.abs(zc) ** 2))
+    e_int = 0.5 * w.Lambda * np.einsum("ijkl,i,j,k,l->", w.V, zc.conj(), zc.conj(), zc, zc)
+    t_pred = 0.05 * n_tot / abs(e_int) if e_int != 0 else float("inf")
+    rho = margin * fh.spectral_radius(model, b) + 1e-9
+    work = torch.empty((4 * b.total,), dtype=torch.complex128, device="cuda")
+    t0 = time.time()
+    series = {k: [] for k in ("t", "n_tot", "Q", "lambda_p", "po_deficit", "vminus")}
+    chunk, t_now = 10, 0.0
+    terms_per_step = len(fh.chebyshev_coefficients(rho * interval))
+    bt = {"t_Q": float("nan"), "t_PO": float("nan"), "t_sqz": float("nan")}
+    while True:
+        res = fh.evolve_chebyshev(model, b, psi, interval, chunk, -rho, rho, every=1, work=work)
+        s = fh.observable_series(w.M, res, interval)
+        first = 0 if not series["t"] else 1  # the chunk's first record repeats the last one
+        for k in series:
+            vals = s[k][first:] + (t_now if k == "t" else 0.0)
+            series[k].extend(vals.tolist())
+        t_now += chunk * interval
+        bt = fh.breaktimes({k: np.array(v) for k, v in series.items()})
+        done = all(np.isfinite(v) for v in bt.values())
+        print(f"  r={r} t={t_now:.3f} Q={series['Q'][-1]:.4f} po={series['po_deficit'][-1]:.4f} "
+              f"V-={series['vminus'][-1]:.4f}", file=sys.stderr, flush=True)
+        if done or t_now >= t_max - 1e-12:
+            break
+    torch.cuda.synchronize()
+    return {"problem": problem, "r": r, "n_tot": n_tot, "sectors": len(sectors), "states": b.total,
+            "t_end": t_now, **bt, "t_sqz_pred": t_pred, "spectral_radius": rho,
+            "h_applies": int(round(t_now / interval)) * terms_per_step, "wall_s": time.time() - t0}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--problem", default="coherent-longrange",
+                    choices=[f"{i}-{p}" for i in ("number", "coherent", "fieldnumber")
+                             for p in ("longrange", "contact+", "contact-")])
+    ap.add_argument("--r", type=int, nargs="+", default=[1, 2, 4])
+    ap.add_argument("--interval", type=float, default=0.02)
+    ap.add_argument("--t-max", type=float, default=20.0)
+    ap.add_argument("--seed", type=int, default=None, help="phase seed (default: the draw matching n_tot |chi| = 0.242)")
+    ap.add_argument("--margin", type=float, default=1.1)
+    ap.add_argument("--out", default=None, help="append JSON lines to this file")
+    a = ap.parse_args()
+    for r in a.r:
+        line = json.dumps(run(a.problem, r, a.interval, a.t_max, a.seed, a.margin))
+        print(line, flush=True)
+        if a.out:
+            with open(a.out, "a") as f:
+                f.write(line + "\n")
+
+
+if __name__ == "__main__":
+    main()
