@@ -663,3 +663,25 @@ def test_paper_superpositions_exact_momentum(init, inter):
         if init == "coherent" and key == "Q":
             assert 0.0 < ref_t < nsteps * dt
         assert abs(got_t - ref_t) <= 1e-8 or (np.isnan(got_t) and np.isnan(ref_t))
+
+
+def test_breaktime_sweep_runner_agrees_with_rk4():
+    """The sweep runner (Chebyshev records every 0.02) and a plain RK4 run
+    (dt = 1e-3, records every 0.02) give the same Q breaktime of the paper's
+    contact problem at r = 1 (Sec. IV.C), up to RK4's truncation."""
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "workloads"))
+    import breaktime_sweep as S
+
+    out = S.run("coherent-contact+", 1, 0.02, 1.0, None, 1.1)
+    assert out["states"] == 8568 and out["sectors"] == 70
+    w = W.paper_problem("coherent", "contact+", 1)
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, W.all_sectors(w.M, S.poisson_nmax(5.0)))
+    psi = fh.init_coherent(b, w.init_params[0])
+    res = fh.evolve_rk4(model, b, psi, 1e-3, 1000, every=20)
+    bt = fh.breaktimes(fh.observable_series(w.M, res, 1e-3))
+    assert 0.5 < out["t_Q"] < 0.7
+    for k in ("t_Q", "t_PO", "t_sqz"):
+        assert abs(out[k] - bt[k]) <= 1e-6, k
