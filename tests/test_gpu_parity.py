@@ -685,3 +685,54 @@ def test_breaktime_sweep_runner_agrees_with_rk4():
     assert 0.5 < out["t_Q"] < 0.7
     for k in ("t_Q", "t_PO", "t_sqz"):
         assert abs(out[k] - bt[k]) <= 1e-6, k
+
+
+# ------------------------------------------------------ full-size samples ---
+def _sample_rows(orc, rng, n):
+    """Random rows plus the first and last row of every fifth sector."""
+    edges = []
+    for s in range(0, len(orc.sectors), 5):
+        if orc.dims[s]:
+            edges += [orc.offsets[s], orc.offsets[s] + orc.dims[s] - 1]
+    return np.unique(np.concatenate([rng.choice(orc.total, n, replace=False), edges])).astype(np.int64)
+
+
+def test_batched_coherent_full_size_sampled():
+    """The batched workload at full size (M=6, 541 sectors, 927,048,304 states):
+    one persistent H psi launch over all sectors, sampled rows against the oracle."""
+    w = W.batched_coherent()
+    orc = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    assert b.total == orc.total == 927_048_304
+    rows = _sample_rows(orc, np.random.default_rng(8), 3000)
+    x = W.periodic_psi(b.total, 3)
+    xd = torch.from_numpy(x).cuda()
+    out = fh.apply_h(model, b, xd)
+    del xd
+    got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del out
+    want = orc.apply_h_rows(x, rows)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_fieldnumber_sixteen_rhs_full_size_sampled():
+    """The 16-draw workload at full size (M=10, N=30, all P: 211,915,132 states
+    x 16 right-hand sides): column q holds e^{i phi_q} x0, so its sampled rows of
+    H psi must be e^{i phi_q} times the oracle's rows for x0; a column mix-up
+    would show the wrong phase."""
+    w = W.fieldnumber_draws()
+    orc = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    assert b.total == orc.total == 211_915_132
+    rows = _sample_rows(orc, np.random.default_rng(9), 2000)
+    x0 = W.periodic_psi(b.total, 5)
+    ph = np.exp(1j * np.linspace(0.3, 5.9, 16))
+    X = torch.from_numpy(x0).cuda()[:, None] * torch.from_numpy(ph).cuda()[None, :]
+    out = fh.apply_h(model, b, X.contiguous())
+    del X
+    got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    del out
+    want = orc.apply_h_rows(x0, rows)
+    scale = np.abs(want).max()
+    for q in range(16):
+        assert np.abs(got[:, q] - ph[q] * want).max() <= 1e-13 * scale, q

@@ -169,6 +169,21 @@ def random_psi(total: int, seed: int, nrhs: int = 1) -> np.ndarray:
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
 
 
+def periodic_psi(total: int, seed: int, chunk: int = 1 << 24) -> np.ndarray:
+    """A cheap full-size test vector: x[i] = T1[i mod p1] + 1j T2[i mod p2] with
+    Gaussian tables and the primes p1 = 1,000,003, p2 = 999,983, so two indices
+    share a value only if they agree mod p1 p2 (~1e12, beyond every sector)."""
+    rng = np.random.default_rng(seed)
+    p1, p2 = 1_000_003, 999_983
+    t1, t2 = rng.standard_normal(p1), rng.standard_normal(p2)
+    x = np.empty(total, np.complex128)
+    for lo in range(0, total, chunk):
+        i = np.arange(lo, min(total, lo + chunk), dtype=np.int64)
+        x.real[lo:lo + len(i)] = t1[i % p1]
+        x.imag[lo:lo + len(i)] = t2[i % p2]
+    return x
+
+
 def all_sectors(M: int, Nmax: int, pmod: int | None = None, Nmin: int = 0):
     pmod = M if pmod is None else pmod
     return [(N, P) for N in range(Nmin, Nmax + 1) for P in range(pmod)]
