@@ -109,7 +109,9 @@ def forms():
     its own workload at full size with a bounded number of steps:
       batched   : one persistent launch per stage over all sectors, the step
                   captured in a HIP graph, vs one launch per sector per stage
-                  (M=6 coherent state, mean 40 bosons, 541 sectors);
+                  (M=6 coherent state, mean 40 bosons, 541 sectors; and the
+                  paper's M=5 long-range coherent problem at r = 4, 176
+                  non-empty sectors of at most 16,451 states);
       multi_rhs : 16 field-number phase draws as one 16-column vector vs the
                   same draws run one at a time (M=10, N=30, all 10 P);
       adjoint   : forward + discrete adjoint (gradients of J), and the
@@ -162,6 +164,36 @@ def forms():
         log(f"  {name}: {steps / t:.3f} steps/s")
     out["batched"] = {
         "workload": "M=6 coherent, mean 40 bosons, N 0..90 x all P, contact V, Lambda=0.05, dt=1e-3",
+        "states": D, "sectors": sum(1 for d in basis.dims if d > 0), "timed_steps": steps,
+        "steps_per_s": sps["batched"], "per_sector_steps_per_s": sps["per_sector"],
+        "speedup": sps["batched"] / sps["per_sector"],
+        "max_abs_diff": float((fin["batched"] - fin["per_sector"]).abs().max()),
+    }
+    del psi0, psi, work, fin
+    model.close()
+    basis.close()
+    torch.cuda.empty_cache()
+
+    # ---- batched vs per sector on many small sectors (the paper's own size)
+    w = W.paper_problem("coherent", "longrange", 4)
+    sectors = W.all_sectors(w.M, 35)  # Poisson(20) weight >= 0.999
+    model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, sectors)
+    D = basis.total
+    log(f"batched (small sectors): {D} states in {len(sectors)} sectors")
+    psi0 = fh.init_coherent(basis, w.init_params[0])
+    work = torch.empty(3 * D, dtype=c128, device="cuda")
+    steps, fin, sps = 200, {}, {}
+    for name, flags in (("batched", fh.FH_GRAPH), ("per_sector", fh.FH_PER_SECTOR)):
+        psi = psi0.clone()
+        sync()
+        with torch.cuda.stream(stream):
+            fh.evolve_rk4(model, basis, psi, 1e-3, 2, flags=flags, work=work)
+            _, t = timed(lambda: fh.evolve_rk4(model, basis, psi, 1e-3, steps, flags=flags, work=work))
+        sps[name], fin[name] = steps / t, psi
+        log(f"  {name}: {steps / t:.1f} steps/s")
+    out["batched_small"] = {
+        "workload": "M=5 coherent, mean 20 bosons (the paper's long-range problem, r = 4, exact momentum), "
+                    "N 0..35 x all P, dt=1e-3",
         "states": D, "sectors": sum(1 for d in basis.dims if d > 0), "timed_steps": steps,
         "steps_per_s": sps["batched"], "per_sector_steps_per_s": sps["per_sector"],
         "speedup": sps["batched"] / sps["per_sector"],
