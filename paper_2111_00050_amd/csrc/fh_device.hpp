@@ -668,8 +668,12 @@ __global__ __launch_bounds__(kTileRows) void occ_table_kernel(OccArgs A) {
 // and every neighbour rank; their terms go into the same sums.  One body per
 // class keeps exactly that class's S^2 complex sums in registers across the
 // persistent tile loop; rows start from their occupation records.  Partials
-// are written with row stride max_class_size.
-template <int M, int C>
+// are written with row stride max_class_size.  With one right-hand side
+// (SC = 16) the rank table is staged times 16, neighbour ranks come out as
+// byte offsets into the sector, and the gathers are buffer loads from an
+// SGPR sector base (empty row pairs load zero from past the end, as in the
+// stage kernel); tile and sector descriptors are scalar loads.
+template <int M, int C, unsigned SC>
 __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     using CB = Combos<M>;
     constexpr int S = CB::class_size(C);
@@ -680,8 +684,8 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     int* sT = smem;
     double* sSq = reinterpret_cast<double*>(smem + lds_sqrt_offset(A.Tn));
     double* red = sSq + A.nsqrt;
-    stage_tables(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
-    const int nrhs = A.nrhs, rhs = A.rhs;
+    stage_tables<SC>(A.T, A.Tn, A.sqrt_tab, A.nsqrt, sT, sSq);
+    const int nrhs = SC == 16 ? 1 : A.nrhs, rhs = SC == 16 ? 0 : A.rhs;
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
@@ -695,17 +699,31 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
             ti = fma(u[p].x, y[p].y, fma(-u[p].y, y[p].x, ti));
         }
     };
+    const __attribute__((address_space(4))) Tile* tiles = (const __attribute__((address_space(4))) Tile*)A.tiles;
+    const __attribute__((address_space(4))) SecInfo* secs =
+        (const __attribute__((address_space(4))) SecInfo*)A.secs;
     const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles);
     for (int t = walk.first; t < walk.end; t += walk.step) {
-        const Tile tl = A.tiles[t];
-        if ((int)threadIdx.x >= tl.nrows) continue;
-        const SecInfo sc = A.secs[tl.sec];
-        const int row = tl.row0 + (int)threadIdx.x;
-        const long long state = sc.off + row;
+        const int tsec = __builtin_amdgcn_readfirstlane(tiles[t].sec);
+        const int row0 = __builtin_amdgcn_readfirstlane(tiles[t].row0);
+        const int nrows = __builtin_amdgcn_readfirstlane(tiles[t].nrows);
+        if ((int)threadIdx.x >= nrows) continue;
+        const unsigned dim = (unsigned)__builtin_amdgcn_readfirstlane(secs[tsec].dim);
+        long long soff;
+        {
+            const unsigned long long o = (unsigned long long)secs[tsec].off;
+            const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)o);
+            const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(o >> 32));
+            soff = (long long)(((unsigned long long)hi << 32) | lo);
+        }
+        const int row = row0 + (int)threadIdx.x;
+        const long long state = soff + row;
+        const unsigned rowS = (unsigned)row * SC;
         int n[M];
         load_occ<M>(A.occ, state, n);
-        int key[M], Cs[M];
-        row_keys<M>(sT, A.Rdim, n, key, Cs);
+        int key[M];
+        unsigned Cs[M];
+        row_keys<M, unsigned>(sT, A.Rdim, n, key, Cs);
         double2 u[NPR], y0[NPR];
 #pragma unroll
         for (int p = 0; p < NPR; ++p) {
@@ -747,10 +765,20 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
             constexpr int NQ = S * (S - 1);
             constexpr int QB = S >= 5 ? kGatherBatch / (2 * NPR) : kGatherBatch / NPR;
             constexpr int NCH = (NQ + QB - 1) / QB;
+            constexpr unsigned kNoGather = 0xFFFFFF00u;
+            __amdgpu_buffer_rsrc_t yrs[NPR];
+            if constexpr (SC == 16) {
+#pragma unroll
+                for (int p = 0; p < NPR; ++p)
+                    yrs[p] = __builtin_amdgcn_make_buffer_rsrc(
+                        (void*)(reinterpret_cast<const double2*>(A.y[p]) + soff), (short)0, (int)(dim * 16u),
+                        kBufferWord3);  // bytes, < 2^32
+            }
             static_for<0, NCH>([&](auto Ch) {
                 constexpr int q0 = decltype(Ch)::value * QB;
                 constexpr int NQC = (NQ - q0) < QB ? (NQ - q0) : QB;
-                long long off[NQC];
+                using off_t = std::conditional_t<SC == 16, unsigned, long long>;
+                off_t off[NQC];
                 static_for<0, NQC>([&](auto Q) {
                     constexpr int q = q0 + decltype(Q)::value;
                     constexpr int r1 = q / (S - 1), tq = q % (S - 1), r2 = tq < r1 ? tq : tq + 1;
@@ -759,19 +787,29 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
                     constexpr int k = CB::pairs.i[p2], l = CB::pairs.j[p2];
                     constexpr int lo = i < k ? i : k;
                     constexpr int hi = j > l ? j : l;
-                    int r = row + (Cs[hi] - Cs[lo]);
+                    unsigned r = rowS + (Cs[hi] - Cs[lo]);
                     static_for<lo + 1, hi + 1>([&](auto Sx) {
                         constexpr int s2 = decltype(Sx)::value;
-                        r -= sT[key[s2] + move_offset<M>(s2, k, l, i, j)];
+                        r -= (unsigned)sT[key[s2] + move_offset<M>(s2, k, l, i, j)];
                     });
-                    const int src = cij[r1] != 0.0 ? r : row;
-                    off[decltype(Q)::value] = (sc.off + src) * nrhs + rhs;
+                    if constexpr (SC == 16) {
+                        off[decltype(Q)::value] = cij[r1] != 0.0 ? r : kNoGather;
+                    } else {
+                        const int src = cij[r1] != 0.0 ? (int)r : row;
+                        off[decltype(Q)::value] = (soff + src) * nrhs + rhs;
+                    }
                 });
                 double2 v[NQC][NPR];
                 static_for<0, NQC>([&](auto Q) {
 #pragma unroll
-                    for (int p = 0; p < NPR; ++p)
-                        v[decltype(Q)::value][p] = reinterpret_cast<const double2*>(A.y[p])[off[decltype(Q)::value]];
+                    for (int p = 0; p < NPR; ++p) {
+                        if constexpr (SC == 16)
+                            v[decltype(Q)::value][p] = __builtin_bit_cast(
+                                double2, __builtin_amdgcn_raw_buffer_load_b128(yrs[p], off[decltype(Q)::value], 0, 0));
+                        else
+                            v[decltype(Q)::value][p] =
+                                reinterpret_cast<const double2*>(A.y[p])[off[decltype(Q)::value]];
+                    }
                 });
                 static_for<0, NQC>([&](auto Q) {
                     constexpr int q = q0 + decltype(Q)::value;
@@ -805,7 +843,10 @@ template <int M>
 __global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
     static_for<0, M>([&](auto Cc) {
         constexpr int c = decltype(Cc)::value;
-        if ((int)blockIdx.y == c) corr_class<M, c>(A);
+        if ((int)blockIdx.y == c) {
+            if (A.nrhs == 1) corr_class<M, c, 16u>(A);
+            else corr_class<M, c, 1u>(A);
+        }
     });
 }
 
