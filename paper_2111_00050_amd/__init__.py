@@ -360,13 +360,16 @@ ONSET_VMINUS = 0.8  # V_-(t_sqz) (Sec. II.E)
 
 def observable_series(M, res, dt, rhs=0):
     """Derived observables of every record of an evolve result: dict of arrays
-    t, n_tot, Q, lambda_p, po_deficit, vminus."""
+    t, n_tot, Q, lambda_p, po_deficit, vminus, and n_modes [nrec, M] (the
+    normalised mode occupations <a_k^+ a_k>)."""
     keys = ("n_tot", "Q", "lambda_p", "po_deficit", "vminus")
     out = {k: np.empty(len(res.records)) for k in keys}
+    out["n_modes"] = np.empty((len(res.records), M))
     for r, rec in enumerate(res.records[:, rhs]):
         d = derive(M, *unpack_moments(M, rec))
         for k in keys:
             out[k][r] = d[k]
+        out["n_modes"][r] = np.real(np.diag(d["M"]))
     out["t"] = np.asarray(res.steps, np.float64) * dt
     return out
 

@@ -675,8 +675,10 @@ def test_breaktime_sweep_runner_agrees_with_rk4():
     sys.path.insert(0, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "workloads"))
     import breaktime_sweep as S
 
-    out = S.run("coherent-contact+", 1, 0.02, 1.0, None, 1.1)
+    out = S.run("coherent-contact+", 1, 0.02, 1.0, None, 1.1, classical=True, t_ref=0.5)
     assert out["states"] == 8568 and out["sectors"] == 70
+    # at t = 0 the quantum occupations are |z_k|^2 up to the 0.999 truncation
+    assert out["classical"]["dev_at_0"] < 5e-3 and out["classical"]["dev_max"] > out["classical"]["dev_at_0"]
     w = W.paper_problem("coherent", "contact+", 1)
     model, b = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, W.all_sectors(w.M, S.poisson_nmax(5.0)))
     psi = fh.init_coherent(b, w.init_params[0])

@@ -8,6 +8,10 @@ has fallen to 0.8 (or --t-max).  Coherent states keep the sectors N <= N_max wit
 the smallest N_max whose Poisson weight is >= 0.999 (Sec. IV.A).  One JSON line
 per r: sizes, the three breaktimes, the squeezing-onset prediction
 t_sqz = 0.05 n_tot / |sum (1/2) Lambda z* z* z z| (Sec. II.E) and the wall time.
+With --classical the classical field of the same initial condition (Sec. III.A:
+sqrt(n_k) for a number state, z for the others) is evolved beside it and the
+distance sum_k |<n_k>(t) - |alpha_k(t)|^2| / n_tot is reported at --t-ref and as
+its maximum (the comparison of Sec. IV.B).
 
     python workloads/breaktime_sweep.py --problem coherent-longrange --r 1 2 4 8
 """
@@ -37,7 +41,8 @@ def poisson_nmax(mean: float, weight: float = 0.999) -> int:
     return N
 
 
-def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float):
+def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float, classical: bool = False,
+        t_ref: float = 1.0):
     import torch
 
     import paper_2111_00050_amd as fh
@@ -64,7 +69,7 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
     rho = margin * fh.spectral_radius(model, b) + 1e-9
     work = torch.empty((4 * b.total,), dtype=torch.complex128, device="cuda")
     t0 = time.time()
-    series = {k: [] for k in ("t", "n_tot", "Q", "lambda_p", "po_deficit", "vminus")}
+    series = {k: [] for k in ("t", "n_tot", "Q", "lambda_p", "po_deficit", "vminus", "n_modes")}
     chunk, t_now = 10, 0.0
     terms_per_step = len(fh.chebyshev_coefficients(rho * interval))
     bt = {"t_Q": float("nan"), "t_PO": float("nan"), "t_sqz": float("nan")}
@@ -74,18 +79,28 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
         first = 0 if not series["t"] else 1  # the chunk's first record repeats the last one
         for k in series:
             vals = s[k][first:] + (t_now if k == "t" else 0.0)
-            series[k].extend(vals.tolist())
+            series[k].extend(list(vals))
         t_now += chunk * interval
         bt = fh.breaktimes({k: np.array(v) for k, v in series.items()})
         done = all(np.isfinite(v) for v in bt.values())
         print(f"  r={r} t={t_now:.3f} Q={series['Q'][-1]:.4f} po={series['po_deficit'][-1]:.4f} "
               f"V-={series['vminus'][-1]:.4f}", file=sys.stderr, flush=True)
-        if done or t_now >= t_max - 1e-12:
+        if (done and (not classical or t_now >= t_ref - 1e-12)) or t_now >= t_max - 1e-12:
             break
     torch.cuda.synchronize()
-    return {"problem": problem, "r": r, "n_tot": n_tot, "sectors": len(sectors), "states": b.total,
-            "t_end": t_now, **bt, "t_sqz_pred": t_pred, "spectral_radius": rho,
-            "h_applies": int(round(t_now / interval)) * terms_per_step, "wall_s": time.time() - t0}
+    out = {"problem": problem, "r": r, "n_tot": n_tot, "sectors": len(sectors), "states": b.total,
+           "t_end": t_now, **bt, "t_sqz_pred": t_pred, "spectral_radius": rho,
+           "h_applies": int(round(t_now / interval)) * terms_per_step, "wall_s": time.time() - t0}
+    if classical:
+        sub = 20
+        nrec = len(series["t"])
+        _, traj = fh.classical_rk4(model, zc, interval / sub, (nrec - 1) * sub, every=sub)
+        ncl = (traj[:, 0, :].abs() ** 2).cpu().numpy()
+        dev = np.abs(np.array(series["n_modes"]) - ncl).sum(axis=1) / n_tot
+        tt = np.array(series["t"])
+        out["classical"] = {"t_ref": t_ref, "dev_at_t_ref": float(np.interp(t_ref, tt, dev)),
+                            "dev_max": float(dev.max()), "dev_at_0": float(dev[0])}
+    return out
 
 
 def main():
@@ -99,9 +114,11 @@ def main():
     ap.add_argument("--seed", type=int, default=None, help="phase seed (default: the draw matching n_tot |chi| = 0.242)")
     ap.add_argument("--margin", type=float, default=1.1)
     ap.add_argument("--out", default=None, help="append JSON lines to this file")
+    ap.add_argument("--classical", action="store_true", help="compare with the classical field")
+    ap.add_argument("--t-ref", type=float, default=1.0, help="time of the classical comparison")
     a = ap.parse_args()
     for r in a.r:
-        line = json.dumps(run(a.problem, r, a.interval, a.t_max, a.seed, a.margin))
+        line = json.dumps(run(a.problem, r, a.interval, a.t_max, a.seed, a.margin, a.classical, a.t_ref))
         print(line, flush=True)
         if a.out:
             with open(a.out, "a") as f:
