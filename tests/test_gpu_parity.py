@@ -738,3 +738,71 @@ def test_fieldnumber_sixteen_rhs_full_size_sampled():
     scale = np.abs(want).max()
     for q in range(16):
         assert np.abs(got[:, q] - ph[q] * want).max() <= 1e-13 * scale, q
+
+
+# ------------------------------------------------- adjoint at full size ---
+def _terminal_J(model, b, psi0, dt, nsteps, obj, mode):
+    psi = psi0.clone()
+    res = fh.evolve_rk4(model, b, psi, dt, nsteps, every=nsteps)
+    d = fh.derive(b.M, *fh.unpack_moments(b.M, res.records[-1, 0]))
+    if obj == fh.FH_J_Q:
+        return d["Q"]
+    if obj == fh.FH_J_PO:
+        return d["po_deficit"]
+    return float(np.real(d["M"][mode, mode]))
+
+
+@pytest.mark.parametrize("which", ["number", "coherent"])
+def test_adjoint_full_size_central_differences(which):
+    """The adjoint workloads at full size (M=6, long range, Lambda = 0.03: a number
+    state N=30, 54,132 states, 3000 steps, checkpoints every 100, J = <n_0>; a
+    coherent state of mean 20, 55,525,372 states, 100 steps, checkpoints every
+    10, J = Q): dJ/dLambda, one dJ/dV entry and (coherent) dJ/dRe alpha_0 and
+    dJ/dIm alpha_1 against central differences of GPU forward runs."""
+    if which == "number":
+        w, nsteps, ck, obj, mode = W.adjoint_number(30), 3000, 100, fh.FH_J_NMODE, 0
+    else:
+        w, nsteps, ck, obj, mode = W.adjoint_coherent(20.0), 100, 10, fh.FH_J_Q, 0
+    b = fh.Basis(w.M, w.sectors)
+
+    def init(alpha=None):
+        if which == "number":
+            return fh.init_number(b, w.init_params)
+        return fh.init_coherent(b, w.init_params if alpha is None else alpha)
+
+    model = fh.Model(w.M, w.omega, w.Lambda, w.V)
+    res = fh.adjoint_rk4(model, b, init(), w.dt, nsteps, ck, obj, mode)
+    J0 = _terminal_J(model, b, init(), w.dt, nsteps, obj, mode)
+    assert abs(res["J"][0] - J0) <= 1e-12 * max(1.0, abs(J0))
+
+    def cd(fn, h):
+        return (fn(h) - fn(-h)) / (2 * h)
+
+    def close(a, want):
+        assert abs(a - want) <= 1e-7 * max(1.0, abs(want)), (a, want)
+
+    h = 1e-6
+    close(res["dLambda"][0], cd(lambda e: _terminal_J(fh.Model(w.M, w.omega, w.Lambda + e, w.V), b, init(),
+                                                      w.dt, nsteps, obj, mode), h))
+    # one momentum-conserving entry of V (1 + 2 = 0 + 3 mod 6)
+    idx = (1, 2, 0, 3)
+
+    def jv(e):
+        V = w.V.copy()
+        V[idx] += e
+        return _terminal_J(fh.Model(w.M, w.omega, w.Lambda, V), b, init(), w.dt, nsteps, obj, mode)
+
+    close(res["dV"][0][idx], cd(jv, 1e-5))
+    if which == "coherent":
+        dre, dim = fh.coherent_vjp(b, w.init_params, res["lambda0"])
+        a0 = np.array(w.init_params, dtype=np.complex128).reshape(w.M)
+
+        def ja(k, unit):
+            def f(e):
+                a = a0.copy()
+                a[k] += unit * e
+                return _terminal_J(model, b, init(a), w.dt, nsteps, obj, mode)
+            return f
+
+        close(dre[0][0], cd(ja(0, 1.0), h))
+        close(dim[0][1], cd(ja(1, 1j), h))
