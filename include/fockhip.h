@@ -164,7 +164,7 @@ fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c64* Mij, con
  * level is never reached.  Non-finite samples are skipped.  FH_EINVAL for a
  * null pointer, n < 0, direction not +-1, a non-finite level or t not strictly
  * increasing (then *out = NaN). */
-fh_status fh_first_crossing(const double* t, const double* y, long long n, double level, int direction,
+fh_status fh_first_crossing(const double* t, const double* y, int64_t n, double level, int direction,
                             double* out);
 
 /* ----------------------------------------------------------------- evolve --

@@ -134,17 +134,17 @@ extern "C" fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c6
     return FH_OK;
 }
 
-extern "C" fh_status fh_first_crossing(const double* t, const double* y, long long n, double level, int direction,
+extern "C" fh_status fh_first_crossing(const double* t, const double* y, int64_t n, double level, int direction,
                                        double* out) {
     if (!out) return FH_EINVAL;
     *out = std::numeric_limits<double>::quiet_NaN();
     if (n < 0 || (n > 0 && (!t || !y)) || (direction != 1 && direction != -1) || !std::isfinite(level))
         return FH_EINVAL;
-    for (long long i = 1; i < n; ++i)
+    for (int64_t i = 1; i < n; ++i)
         if (!(t[i] > t[i - 1])) return FH_EINVAL;
     // past(v): the sample lies at or beyond the level in the crossing direction
     auto past = [&](double v) { return direction > 0 ? v >= level : v <= level; };
-    for (long long i = 0; i < n; ++i) {
+    for (int64_t i = 0; i < n; ++i) {
         if (!std::isfinite(y[i]) || !past(y[i])) continue;
         if (i == 0 || !std::isfinite(y[i - 1])) {
             *out = t[i];
