@@ -806,3 +806,41 @@ def test_adjoint_full_size_central_differences(which):
 
         close(dre[0][0], cd(ja(0, 1.0), h))
         close(dim[0][1], cd(ja(1, 1j), h))
+
+
+def test_paper_coherent_full_size_sampled_exact_sectors():
+    """The paper's long-range coherent problem at r = 16 (n_tot = 80; Poisson
+    weight >= 0.999 keeps N <= 109: 146,803,272 states in 550 periodic sectors):
+    one H psi launch over the periodic basis against the oracle's exact sectors
+    (Sigma j n_j fixed) on sampled rows.  The vector is a function of the
+    occupation vector, so both bases hold the same state; rows are matched by
+    occupations through the GPU rank entry point."""
+    import os
+    import sys
+
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "workloads"))
+    import breaktime_sweep as S
+
+    w = W.paper_problem("coherent", "longrange", 16)
+    Nmax = S.poisson_nmax(80.0)
+    assert Nmax == 109
+    b = fh.Basis(w.M, W.all_sectors(w.M, Nmax))
+    assert b.total == 146_803_272
+    model = fh.Model(w.M, w.omega, w.Lambda, w.V)
+    x = W.occupation_psi(b.occupations().cpu().numpy(), 11)
+    out = fh.apply_h(model, b, torch.from_numpy(x).cuda())
+    del x
+    exact = [(40, 80), (80, 161), (100, 200), (109, 218), (109, 300), (109, 0), (109, 1), (109, 436), (1, 3)]
+    orc = Oracle(w.M, Nmax * (w.M - 1) + 1, w.omega, w.Lambda, w.V, exact)
+    xo = W.occupation_psi(orc.all_occupations(), 11)
+    rng = np.random.default_rng(12)
+    for s, (N, P) in enumerate(exact):
+        loc = np.unique(np.concatenate([rng.choice(orc.dims[s], min(400, orc.dims[s]), replace=False),
+                                        [0, orc.dims[s] - 1]]))
+        occ = np.ascontiguousarray(orc.occupations(s)[loc])
+        ps = N * w.M + P % w.M  # periodic sector (N, P mod M) in all_sectors order
+        grow = b.rank(ps, torch.from_numpy(occ).cuda()).cpu().numpy()
+        assert np.all(grow >= 0)
+        got = out[torch.from_numpy(grow + b.offsets[ps]).cuda()].cpu().numpy()
+        want = orc.apply_h_rows(xo, loc + orc.offsets[s])
+        assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max()), (N, P)

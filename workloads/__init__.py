@@ -184,6 +184,30 @@ def periodic_psi(total: int, seed: int, chunk: int = 1 << 24) -> np.ndarray:
     return x
 
 
+def occupation_psi(occ: np.ndarray, seed: int, chunk: int = 1 << 24) -> np.ndarray:
+    """A test vector that is a function of the occupation vector alone, so that
+    two bases ordering the same states differently hold the same state:
+    x(n) from a 64-bit mix (splitmix64 finaliser) of n's base-256 digits and the
+    seed, real and imaginary parts uniform in [-1, 1)."""
+    occ = np.asarray(occ, dtype=np.uint8)
+    out = np.empty(len(occ), np.complex128)
+    m1, m2 = np.uint64(0xBF58476D1CE4E5B9), np.uint64(0x94D049BB133111EB)
+    for lo in range(0, len(occ), chunk):
+        o = occ[lo:lo + chunk].astype(np.uint64)
+        z = np.full(len(o), (seed * 0x9E3779B97F4A7C15) & 0xFFFFFFFFFFFFFFFF, np.uint64)
+        for m in range(o.shape[1]):
+            z = z * np.uint64(257) + o[:, m]
+        z = z + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * m1
+        z = (z ^ (z >> np.uint64(27))) * m2
+        z = z ^ (z >> np.uint64(31))
+        re = (z >> np.uint64(32)).astype(np.float64) / 2.0 ** 31 - 1.0
+        im = (z & np.uint64(0xFFFFFFFF)).astype(np.float64) / 2.0 ** 31 - 1.0
+        out.real[lo:lo + len(o)] = re
+        out.imag[lo:lo + len(o)] = im
+    return out
+
+
 def all_sectors(M: int, Nmax: int, pmod: int | None = None, Nmin: int = 0):
     pmod = M if pmod is None else pmod
     return [(N, P) for N in range(Nmin, Nmax + 1) for P in range(pmod)]
