@@ -62,6 +62,10 @@ def test_host_validation_paths():
     P2 = np.array([0, 3], np.int32)
     assert lib.fh_basis_create(M, M, 2, fh._np_ptr(N), fh._np_ptr(P2), ctypes.byref(h)) == fh.FH_EINVAL
     assert lib.fh_basis_create(M, M, 0, fh._np_ptr(N), fh._np_ptr(P), ctypes.byref(h)) == fh.FH_EINVAL
+    # a sector of 2^28 states or more (M=10, N=42: 304,232,500) is refused before any device work
+    big_N, big_P = np.array([42], np.int32), np.array([0], np.int32)
+    assert lib.fh_basis_create(10, 10, 1, fh._np_ptr(big_N), fh._np_ptr(big_P), ctypes.byref(h)) == fh.FH_EOVERFLOW
+    assert b"2^28" in lib.fh_last_error()
     assert lib.fh_adjoint_work_states(0, 10) == -1
     assert lib.fh_adjoint_work_states(3000, 100) == 30 + 100 + 10
     assert lib.fh_adjoint_work_states_kept(3000, 100) == 30 + 400 + 10

@@ -844,3 +844,24 @@ def test_paper_coherent_full_size_sampled_exact_sectors():
         got = out[torch.from_numpy(grow + b.offsets[ps]).cuda()].cpu().numpy()
         want = orc.apply_h_rows(xo, loc + orc.offsets[s])
         assert np.abs(got - want).max() <= 1e-13 * max(1.0, np.abs(want).max()), (N, P)
+
+
+def test_largest_sector_below_the_limit_sampled():
+    """M=8, N=68, P=0: 248,104,707 states, 3.97 GB per vector, the largest M=8
+    sector under the 2^28-state limit, where the one-column kernel's 32-bit
+    byte offsets come closest to 2^32: sampled rows of H psi (incl. the last
+    rows) against the oracle."""
+    M, N = 8, 68
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    orc = Oracle(M, M, omega, 0.02, V, [(N, 0)])
+    b = fh.Basis(M, [(N, 0)])
+    assert b.total == orc.total == 248_104_707
+    model = fh.Model(M, omega, 0.02, V)
+    x = W.periodic_psi(b.total, 13)
+    out = fh.apply_h(model, b, torch.from_numpy(x).cuda())
+    rng = np.random.default_rng(14)
+    rows = np.unique(np.concatenate([rng.choice(b.total, 3000, replace=False),
+                                     np.arange(b.total - 300, b.total), np.arange(300)])).astype(np.int64)
+    got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
+    want = orc.apply_h_rows(x, rows)
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
