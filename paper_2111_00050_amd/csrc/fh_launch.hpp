@@ -79,6 +79,9 @@ void launch_reduce_partials(const double* part, int ngroups, int G, int stride, 
 // One RK4 stage of the tangent d psi/d Lambda (n complex entries; see util.hip).
 void launch_tangent_stage(const double* hz, const double* gy, const double* base, double* acc, double* next,
                           double* baseout, long long n, int mode, double a, double c0, double b, hipStream_t s);
+// RK4 stage update as a separate pass (h = H y, may be next or baseout).
+void launch_rk4_update(const double* h, const double* base, double* acc, double* next, double* baseout, long long n,
+                       int mode, double ks_re, double ks_im, double a, double c0, double b, hipStream_t s);
 // Re sum conj(g) z over column rhs: writes per-block partials, returns their count.
 int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
                   hipStream_t s);

@@ -65,6 +65,34 @@ __global__ void tangent_stage_kernel(const double* hz, const double* gy, const d
     }
 }
 
+// The RK4 update of a stage as its own pass over n complex entries, for the
+// mode counts where the stage kernel runs without its fused epilogue: h = H y
+// on entry (h may be the destination, next or baseout, and is read before it
+// is written); k = ks h; FIRST: acc = base + a k, next = c0 base + b k;
+// MID: acc += a k, next = c0 base + b k; LAST: baseout = acc + a k.  Same
+// arithmetic as the fused epilogue.
+__global__ void rk4_update_kernel(const double* h, const double* base, double* acc, double* next, double* baseout,
+                                  long long n, int mode, double ks_re, double ks_im, double a, double c0, double b) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double hr = h[2 * i], hi = h[2 * i + 1];
+        const double kr = ks_re * hr - ks_im * hi;
+        const double ki = ks_re * hi + ks_im * hr;
+        if (mode == kLast) {
+            const double ar = acc[2 * i], ai = acc[2 * i + 1];
+            baseout[2 * i] = fma(a, kr, ar);
+            baseout[2 * i + 1] = fma(a, ki, ai);
+            continue;
+        }
+        const double br = base[2 * i], bi = base[2 * i + 1];
+        const double ar = mode == kFirst ? br : acc[2 * i], ai = mode == kFirst ? bi : acc[2 * i + 1];
+        acc[2 * i] = fma(a, kr, ar);
+        acc[2 * i + 1] = fma(a, ki, ai);
+        next[2 * i] = fma(b, kr, c0 * br);
+        next[2 * i + 1] = fma(b, ki, c0 * bi);
+    }
+}
+
 // Per-block partial sums of Re sum_i conj(g_i) z_i over column rhs of a
 // [total][nrhs] complex layout; partial[blockIdx.x] (fixed-order tree in the block).
 __global__ void dot_re_kernel(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial) {
@@ -165,6 +193,12 @@ void launch_tangent_stage(const double* hz, const double* gy, const double* base
     if (n > 0)
         hipLaunchKernelGGL(tangent_stage_kernel, dim3(grid_for(n)), dim3(256), 0, s, hz, gy, base, acc, next, baseout,
                            n, mode, a, c0, b);
+}
+void launch_rk4_update(const double* h, const double* base, double* acc, double* next, double* baseout, long long n,
+                       int mode, double ks_re, double ks_im, double a, double c0, double b, hipStream_t s) {
+    if (n > 0)
+        hipLaunchKernelGGL(rk4_update_kernel, dim3(grid_for(n)), dim3(256), 0, s, h, base, acc, next, baseout, n, mode,
+                           ks_re, ks_im, a, c0, b);
 }
 int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
                   hipStream_t s) {

@@ -865,3 +865,36 @@ def test_largest_sector_below_the_limit_sampled():
     got = out[torch.from_numpy(rows).cuda()].cpu().numpy()
     want = orc.apply_h_rows(x, rows)
     assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_m10_stages_with_separate_update():
+    """M = 10: RK4 and the second-order step against the oracle; 16 columns
+    (where a stage is an H y pass plus a separate update pass) bitwise equal to
+    single columns (fused epilogue); the adjoint's dJ/dLambda against the
+    oracle's adjoint."""
+    M, Lam, dt = 10, 0.2, 4e-3
+    sectors = [(5, p) for p in range(M)] + [(4, 3)]
+    omega, V = W.omega_linear(M), W.V_random_symmetric(M, 21)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    al = np.stack([W.coherent_amplitudes(s, M, 1.2) for s in (71, 72)])
+    z = W.phase_draws([1, 0, 2, 0, 0, 1, 0, 1, 0, 0], range(5, 21))
+    psi = fh.init_fieldnumber(b, z[0])
+    res = fh.evolve_rk4(model, b, psi, dt, 60, every=30)
+    ref, recs = _oracle_run(orc, states.fieldnumber_state(orc, z[0]), dt, 60, 30)
+    assert np.linalg.norm(psi.cpu().numpy() - ref) <= 1e-10
+    _check_records(M, res, recs)
+    psi = fh.init_fieldnumber(b, z[0])
+    fh.evolve_taylor2(model, b, psi, dt, 40, c2=0.5)
+    ref2, _ = evolve.taylor2(orc, states.fieldnumber_state(orc, z[0]), dt, 40, c2=0.5)
+    assert np.linalg.norm(psi.cpu().numpy() - ref2) <= 1e-10
+    both = fh.init_fieldnumber(b, z)
+    fh.evolve_rk4(model, b, both, dt, 25)
+    for q in (0, 7, 15):
+        one = fh.init_fieldnumber(b, z[q])
+        fh.evolve_rk4(model, b, one, dt, 25)
+        assert torch.equal(both[:, q].contiguous(), one)
+    ref3 = evolve.adjoint(orc, states.fieldnumber_state(orc, z[1]), dt, 20, evolve.objective_PO(orc))
+    adj = fh.adjoint_rk4(model, b, fh.init_fieldnumber(b, z[1]), dt, 20, 6, fh.FH_J_PO)
+    assert abs(adj["J"][0] - ref3["J"]) <= 1e-10
+    assert abs(adj["dLambda"][0] - ref3["dLambda"]) <= 1e-9 * max(1, abs(ref3["dLambda"]))
+    del al
