@@ -7,7 +7,9 @@ is evolved on the GPU with the Chebyshev propagator in record intervals of
 has fallen to 0.8 (or --t-max).  Coherent states keep the sectors N <= N_max with
 the smallest N_max whose Poisson weight is >= 0.999 (Sec. IV.A).  One JSON line
 per r: sizes, the three breaktimes, the squeezing-onset prediction
-t_sqz = 0.05 n_tot / |sum (1/2) Lambda z* z* z z| (Sec. II.E) and the wall time.
+t_sqz = 0.05 n_tot / |sum (1/2) Lambda z* z* z z| (Sec. II.E), the deepest
+squeezing V_min within the run and its time tau_min = n_tot |chi| t_min
+(Sec. IV.E), and the wall time.
 With --classical the classical field of the same initial condition (Sec. III.A:
 sqrt(n_k) for a number state, z for the others) is evolved beside it and the
 distance sum_k |<n_k>(t) - |alpha_k(t)|^2| / n_tot is reported at --t-ref and as
@@ -91,6 +93,22 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
     out = {"problem": problem, "r": r, "n_tot": n_tot, "sectors": len(sectors), "states": b.total,
            "t_end": t_now, **bt, "t_sqz_pred": t_pred, "spectral_radius": rho,
            "h_applies": int(round(t_now / interval)) * terms_per_step, "wall_s": time.time() - t0}
+    # deepest squeezing within the run (Sec. IV.E): V_min and tau_min = n_tot |chi| t_min,
+    # the minimum refined by the parabola through the three samples around it
+    vm = np.array(series["vminus"], dtype=np.float64)
+    tt = np.array(series["t"], dtype=np.float64)
+    if np.isfinite(vm).any():
+        k = int(np.nanargmin(vm))
+        t_min, v_min = float(tt[k]), float(vm[k])
+        if 0 < k < len(vm) - 1 and np.all(np.isfinite(vm[k - 1:k + 2])):
+            y0, y1, y2 = vm[k - 1], vm[k], vm[k + 1]
+            den = y0 - 2.0 * y1 + y2
+            if den > 0:
+                off = 0.5 * (y0 - y2) / den
+                t_min = float(tt[k] + off * (tt[k + 1] - tt[k]))
+                v_min = float(y1 - 0.25 * (y0 - y2) * off)
+        n_chi = abs(e_int) / n_tot
+        out.update(vminus_min=v_min, t_vminus_min=t_min, tau_min=n_chi * t_min, n_chi=n_chi)
     if classical:
         sub = 20
         nrec = len(series["t"])
