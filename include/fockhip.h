@@ -17,7 +17,11 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - Modes j = 0..M-1 (1 <= M <= 10 on the GPU path); pmod must equal M
- *    (periodic momentum grid).  Occupations are uint8 (N <= 255).
+ *    (periodic momentum grid).  Occupations are uint8 (N <= 255).  The
+ *    paper's exact momentum (sum_j j n_j, no wrap-around) is covered by an
+ *    interaction that conserves it exactly (nonzero V only where
+ *    i + j == k + l): every periodic sector is then a union of exact sectors
+ *    that H never couples, and a state inside one exact sector stays there.
  *  - Inside a sector, basis states are ordered lexicographically ascending
  *    with n_0 the most significant entry; a state's index in that order is its
  *    rank.  State vectors concatenate sectors in the order given to
