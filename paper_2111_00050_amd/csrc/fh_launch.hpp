@@ -82,6 +82,10 @@ void launch_tangent_stage(const double* hz, const double* gy, const double* base
 // RK4 stage update as a separate pass (h = H y, may be next or baseout).
 void launch_rk4_update(const double* h, const double* base, double* acc, double* next, double* baseout, long long n,
                        int mode, double ks_re, double ks_im, double a, double c0, double b, hipStream_t s);
+// G y = (H y - diag(omega . n) y) / Lambda from h = H y (see util.hip).
+void launch_interaction_part(const double* h, const double* y, const unsigned char* occ, int stride, int M,
+                             const double* omega, double inv_lambda, long long nstates, int nrhs, double* gy,
+                             hipStream_t s);
 // Re sum conj(g) z over column rhs: writes per-block partials, returns their count.
 int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
                   hipStream_t s);

@@ -93,6 +93,23 @@ __global__ void rk4_update_kernel(const double* h, const double* base, double* a
     }
 }
 
+// The interaction part of H applied to y from h = H y: G y = (h - diag(omega . n) y) / Lambda,
+// over nstates * nrhs complex entries ([state][rhs]); occupations from the basis's records
+// (stride bytes per state).  The kinetic diagonal is summed in the stage kernel's order.
+__global__ void interaction_part_kernel(const double* h, const double* y, const unsigned char* occ, int stride, int M,
+                                        const double* omega, double inv_lambda, long long nstates, int nrhs,
+                                        double* gy) {
+    const long long n = nstates * nrhs;
+    const long long step = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += step) {
+        const unsigned char* r = occ + (i / nrhs) * stride;
+        double kin = 0.0;
+        for (int j = 0; j < M; ++j) kin = fma(omega[j], (double)r[j], kin);
+        gy[2 * i] = (h[2 * i] - kin * y[2 * i]) * inv_lambda;
+        gy[2 * i + 1] = (h[2 * i + 1] - kin * y[2 * i + 1]) * inv_lambda;
+    }
+}
+
 // Per-block partial sums of Re sum_i conj(g_i) z_i over column rhs of a
 // [total][nrhs] complex layout; partial[blockIdx.x] (fixed-order tree in the block).
 __global__ void dot_re_kernel(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial) {
@@ -199,6 +216,13 @@ void launch_rk4_update(const double* h, const double* base, double* acc, double*
     if (n > 0)
         hipLaunchKernelGGL(rk4_update_kernel, dim3(grid_for(n)), dim3(256), 0, s, h, base, acc, next, baseout, n, mode,
                            ks_re, ks_im, a, c0, b);
+}
+void launch_interaction_part(const double* h, const double* y, const unsigned char* occ, int stride, int M,
+                             const double* omega, double inv_lambda, long long nstates, int nrhs, double* gy,
+                             hipStream_t s) {
+    if (nstates > 0)
+        hipLaunchKernelGGL(interaction_part_kernel, dim3(grid_for(nstates * nrhs)), dim3(256), 0, s, h, y, occ, stride,
+                           M, omega, inv_lambda, nstates, nrhs, gy);
 }
 int launch_dot_re(const double* g, const double* z, long long total, int nrhs, int rhs, double* partial,
                   hipStream_t s) {

@@ -898,3 +898,18 @@ def test_m10_stages_with_separate_update():
     assert abs(adj["J"][0] - ref3["J"]) <= 1e-10
     assert abs(adj["dLambda"][0] - ref3["dLambda"]) <= 1e-9 * max(1, abs(ref3["dLambda"]))
     del al
+
+
+def test_tangent_at_zero_interaction():
+    """Lambda = 0 takes the tangent's other branch (G y as its own application):
+    dJ/dLambda at Lambda = 0 against the oracle's adjoint and the GPU adjoint."""
+    M, dt, nsteps = 4, 5e-3, 20
+    sectors = W.all_sectors(M, 8)
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    orc, model, b = _pair(M, sectors, omega, 0.0, V)
+    alpha = W.coherent_amplitudes(33, M, 1.4)
+    ref = evolve.adjoint(orc, states.coherent_state(orc, alpha), dt, nsteps, evolve.objective_Q(orc))
+    tan = fh.tangent_rk4(model, b, fh.init_coherent(b, alpha), dt, nsteps, fh.FH_J_Q)
+    adj = fh.adjoint_rk4(model, b, fh.init_coherent(b, alpha), dt, nsteps, 5, fh.FH_J_Q)
+    assert abs(tan["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
+    assert abs(tan["dLambda"][0] - adj["dLambda"][0]) <= 1e-10 * max(1, abs(adj["dLambda"][0]))
