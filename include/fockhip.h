@@ -151,11 +151,23 @@ typedef struct {
     double vminus;     /* Eq. (generalVminus) for O = a^p of Eq. (a_op); NaN if the
                           top eigenvalue is degenerate to 1e-8 relative */
 } fh_obs_scalars;
-/* Derived scalars from moments (host only; no device work).  xi[M] (may be
- * NULL) receives the principal eigenvector; vminus_mode[M] (may be NULL) the
- * per-mode V_- with O = a_i. */
+/* Derived observables from the unnormalised moments of fh_moments (host
+ * only; no device work).  Every expectation value is divided by norm2 =
+ * <psi|psi> (truncated coherent states are not normalised).
+ * Outputs (host; each array may be NULL):
+ *   s              the scalars above;
+ *   xi[M]          principal eigenvector of M_ij (Eq. POcriterion, Eq. a_op),
+ *                  phase arbitrary;
+ *   vminus_mode[M] per-mode V_- of Eq. (generalVminus) with O = a_i;
+ *   a_n[M], Mij_n[M*M], Akl_n[M*M]  the normalised <a_i>, <a_i^+ a_j>,
+ *                  <a_k a_l> (row-major, like the inputs);
+ *   n_modes[M]     the mode occupations <a_i^+ a_i> (Sec. II.B), whose sum
+ *                  is n_tot.
+ * FH_ESTATE (every output NaN) when norm2 is not positive and finite, or when
+ * n_tot or lambda_p is not finite; FH_EINVAL for a null input or s. */
 fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c64* Mij, const fh_c64* Akl,
-                    fh_obs_scalars* s, fh_c64* xi, double* vminus_mode);
+                    fh_obs_scalars* s, fh_c64* xi, double* vminus_mode, fh_c64* a_n, fh_c64* Mij_n,
+                    fh_c64* Akl_n, double* n_modes);
 
 /* ------------------------------------------------------------ breaktimes --
  * First time a sampled observable reaches a level: the quantum breaktimes
@@ -172,6 +184,9 @@ fh_status fh_first_crossing(const double* t, const double* y, int64_t n, double 
                             double* out);
 
 /* ----------------------------------------------------------------- evolve --
+ * Time evolution of each retained sector under the Schroedinger equation
+ * d|phi>/dt = -i H |phi> (Sec. II.A; solved sector by sector with the
+ * projected H^j of Sec. III.B, where the paper's own step is Eq. Q_int):
  * nsteps classical RK4 steps of dt on d psi/dt = -i H psi, in place on psi
  * (device, total*nrhs).  work: device scratch of 3*total*nrhs fh_c64.
  * If obs_every > 0, moments of every rhs are taken at steps 0, obs_every,
@@ -302,8 +317,13 @@ fh_status fh_spectral_radius(const fh_model* m, const fh_basis* b, fh_c64* work,
  * (the interaction term of Eq. Ham with Lambda = 1), differentiated step by
  * step like the discrete RK4 map, and returns J(psi_T) and
  * dJ/dLambda = Re <2 dJ/d conj(psi_T), dpsi_T> for the objectives above.
- * Needs no checkpoints: work is 8*total*nrhs fh_c64 (device); three H psi
- * per stage.  A memory-light cross-check of fh_adjoint_rk4's dJ/dLambda. */
+ * Needs no checkpoints: work is 8*total*nrhs fh_c64 (device).  Two H psi
+ * per stage (H y gives both the psi update and G y = (H y - diag(omega.n) y)
+ * / Lambda) unless |Lambda| is so small against the kinetic scale that this
+ * subtraction would cost more than 1e-12 relative accuracy (eps Nmax
+ * max|omega| > 1e-12 |Lambda| Nmax^2 max|V| / 2), and always at Lambda = 0:
+ * then three (G y by its own application).  A memory-light cross-check of
+ * fh_adjoint_rk4's dJ/dLambda. */
 fh_status fh_tangent_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64* psi, fh_c64* dpsi, fh_c64* work,
                          double dt, int64_t nsteps, int objective, int obj_mode, double* J, double* dJ_dLambda,
                          void* stream);

@@ -69,7 +69,7 @@ SIGNATURES = {
     "fh_init_fieldnumber": (_I, [_P, _P, _I, _P, _P]),
     "fh_apply_h": (_I, [_P, _P, _I, _P, _P, _P]),
     "fh_moments": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
-    "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P]),
+    "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "fh_first_crossing": (_I, [_P, _P, _I64, _D, _I, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
     "fh_evolve_taylor2": (_I, [_P, _P, _I, _P, _P, _D, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
@@ -324,20 +324,24 @@ def unpack_moments(M, rec):
 
 
 def derive(M, norm2, a, Mij, Akl):
-    """Q (Eq. Qparam), lambda_p and PO deficit (Eq. POcriterion), V_- (Eq. generalVminus)."""
+    """Q (Eq. Qparam), lambda_p and PO deficit (Eq. POcriterion), V_- (Eq. generalVminus),
+    and the moments divided by norm2 (keys a, M, A, n_modes), all from fh_derive."""
     a = np.ascontiguousarray(a, np.complex128)
     Mij = np.ascontiguousarray(Mij, np.complex128)
     Akl = np.ascontiguousarray(Akl, np.complex128)
     s = fh_obs_scalars()
     xi = np.zeros(M, np.complex128)
     vm = np.zeros(M)
+    an = np.zeros(M, np.complex128)
+    Mn = np.zeros((M, M), np.complex128)
+    An = np.zeros((M, M), np.complex128)
+    nm = np.zeros(M)
     st = _lib.fh_derive(int(M), float(norm2), _np_ptr(a), _np_ptr(Mij), _np_ptr(Akl), ctypes.byref(s), _np_ptr(xi),
-                        _np_ptr(vm))
+                        _np_ptr(vm), _np_ptr(an), _np_ptr(Mn), _np_ptr(An), _np_ptr(nm))
     if st not in (FH_OK, FH_ESTATE):
         _check(st)
     out = {k: getattr(s, k) for k, _ in fh_obs_scalars._fields_}
-    out.update(a=a / norm2 if norm2 else a, M=Mij / norm2 if norm2 else Mij, A=Akl / norm2 if norm2 else Akl,
-               xi=xi, vminus_mode=vm)
+    out.update(a=an, M=Mn, A=An, n_modes=nm, xi=xi, vminus_mode=vm)
     return out
 
 
@@ -369,7 +373,7 @@ def observable_series(M, res, dt, rhs=0):
         d = derive(M, *unpack_moments(M, rec))
         for k in keys:
             out[k][r] = d[k]
-        out["n_modes"][r] = np.real(np.diag(d["M"]))
+        out["n_modes"][r] = d["n_modes"]
     out["t"] = np.asarray(res.steps, np.float64) * dt
     return out
 

@@ -1344,7 +1344,8 @@ fh_status terminal_coefficients(int M, const double* rec, int objective, int obj
             Av[q] = fh_c64{rec[1 + 2 * M + 2 * M * M + 2 * q], rec[2 + 2 * M + 2 * M * M + 2 * q]};
         }
         fh_obs_scalars sc{};
-        fh_status st = fh_derive(M, nu, av.data(), Mv.data(), Av.data(), &sc, xi.data(), nullptr);
+        fh_status st = fh_derive(M, nu, av.data(), Mv.data(), Av.data(), &sc, xi.data(), nullptr, nullptr, nullptr, nullptr,
+                                 nullptr);
         if (st != FH_OK) return st;
         *J = 1.0 - sc.lambda_p / n;
         setc(1, 2.0 * sc.lambda_p / (n * n * nu));
@@ -1622,13 +1623,25 @@ fh_status fh_tangent_rk4(const fh_model* m, const fh_basis* b, int nrhs, fh_c64*
         } zs[4] = {{Z, zA, kFirst, dt / 6, dt / 2}, {zA, zB, kMid, dt / 3, dt / 2}, {zB, zA, kMid, dt / 3, dt},
                    {zA, nullptr, kLast, dt / 6, 0.0}};
         StageArgs* ps[4] = {&s1, &s2, &s3, &s4};
-        // With Lambda != 0 the psi stage is H y into the stage's destination buffer (next, or
-        // psi itself in the last stage; neither is read by that pass), G y = (H y - diag(omega . n) y)
-        // / Lambda from it, and the psi update as a separate pass with the fused epilogue's
-        // arithmetic: two H applications per stage instead of three.  The subtraction costs
-        // about eps * max|omega . n| / |Lambda G y| of relative accuracy in G y.  With Lambda = 0,
-        // G y is an application of G itself.
-        const bool via_h = m->Lambda != 0.0;
+        // Unless Lambda is tiny, the psi stage is H y into the stage's destination buffer (next,
+        // or psi itself in the last stage; neither is read by that pass), G y = (H y -
+        // diag(omega . n) y) / Lambda from it, and the psi update as a separate pass with the
+        // fused epilogue's arithmetic: two H applications per stage instead of three.  The
+        // subtraction costs about eps * max|omega . n| / |Lambda G| of relative accuracy in G y.
+        // Bound max|omega . n| by Nmax max|omega_j| and |G| by Nmax^2 max|V| / 2 (every pair
+        // term carries at most n(n-1) <= Nmax^2 bosons' worth of sqrt factors); when that ratio
+        // would cost more than 1e-12 relative (and always at Lambda = 0), G y is an application
+        // of G itself: three H applications per stage.
+        bool via_h = false;
+        {
+            double wmax = 0.0, vmax = 0.0;
+            for (double w : m->omega) wmax = std::max(wmax, std::fabs(w));
+            for (double v : m->V) vmax = std::max(vmax, std::fabs(v));
+            const double nmax = std::max(1, b->Nmax);
+            const double kin = nmax * wmax, inter = 0.5 * nmax * nmax * vmax;
+            via_h = m->Lambda != 0.0 && inter > 0.0 &&
+                    std::numeric_limits<double>::epsilon() * kin <= 1e-12 * std::fabs(m->Lambda) * inter;
+        }
         for (int64_t step = 0; step < nsteps; ++step) {
             for (int q = 0; q < 4; ++q) {
                 StageArgs ga = gb, ha = hb;

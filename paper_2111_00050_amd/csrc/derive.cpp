@@ -5,7 +5,9 @@
 //   lambda_p = largest eigenvalue of M_ij = <a_i^+ a_j>  (Eq. POcriterion)
 //   O        = sum_k xi_k a_k, xi the principal eigenvector (Eq. a_op)
 //   V_-      = 1 + 2 (<O^+ O> - |<O>|^2) - 2 |<O^2> - <O>^2|   (Eq. generalVminus)
-// All expectations are divided by norm2 = <psi|psi>.  The Hermitian
+// All expectations are divided by norm2 = <psi|psi> (the state need not be
+// normalised: truncated coherent states are not); the normalised moments and
+// the mode occupations <a_i^+ a_i> are returned as well.  The Hermitian
 // eigenproblem is solved with cyclic complex Jacobi rotations.
 #include <cmath>
 #include <complex>
@@ -74,12 +76,24 @@ void jacobi_hermitian(int n, std::vector<cd>& A, std::vector<cd>& V) {
 }  // namespace
 
 extern "C" fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c64* Mij, const fh_c64* Akl,
-                               fh_obs_scalars* s, fh_c64* xi_out, double* vminus_mode) {
+                               fh_obs_scalars* s, fh_c64* xi_out, double* vminus_mode, fh_c64* a_norm,
+                               fh_c64* Mij_norm, fh_c64* Akl_norm, double* n_modes) {
     if (M < 1 || M > 64 || !a || !Mij || !Akl || !s) return FH_EINVAL;
     const double nan = std::numeric_limits<double>::quiet_NaN();
     s->norm2 = norm2;
     if (!(norm2 > 0.0) || !std::isfinite(norm2)) {
         s->n_tot = s->Q = s->lambda_p = s->po_deficit = s->vminus = nan;
+        const fh_c64 cnan{nan, nan};
+        for (int i = 0; i < M; ++i) {
+            if (xi_out) xi_out[i] = cnan;
+            if (vminus_mode) vminus_mode[i] = nan;
+            if (a_norm) a_norm[i] = cnan;
+            if (n_modes) n_modes[i] = nan;
+        }
+        for (int q = 0; q < M * M; ++q) {
+            if (Mij_norm) Mij_norm[q] = cnan;
+            if (Akl_norm) Akl_norm[q] = cnan;
+        }
         return FH_ESTATE;
     }
     std::vector<cd> av(M), Mm((size_t)M * M), Am((size_t)M * M);
@@ -88,6 +102,15 @@ extern "C" fh_status fh_derive(int M, double norm2, const fh_c64* a, const fh_c6
         Mm[q] = cd(Mij[q].re, Mij[q].im) / norm2;
         Am[q] = cd(Akl[q].re, Akl[q].im) / norm2;
     }
+    auto put = [](const cd& z) { return fh_c64{z.real(), z.imag()}; };
+    if (a_norm)
+        for (int i = 0; i < M; ++i) a_norm[i] = put(av[i]);
+    if (Mij_norm)
+        for (int q = 0; q < M * M; ++q) Mij_norm[q] = put(Mm[q]);
+    if (Akl_norm)
+        for (int q = 0; q < M * M; ++q) Akl_norm[q] = put(Am[q]);
+    if (n_modes)
+        for (int i = 0; i < M; ++i) n_modes[i] = Mm[(size_t)i * M + i].real();
     double ntot = 0.0, sa = 0.0;
     for (int i = 0; i < M; ++i) {
         ntot += Mm[(size_t)i * M + i].real();

@@ -143,3 +143,41 @@ def test_first_crossing_host_only():
     s = {"t": t, "Q": 0.1 * t, "po_deficit": 0.05 * t, "vminus": 1.0 - 0.1 * t}
     bt = fh.breaktimes(s)
     assert abs(bt["t_Q"] - 1.5) < 1e-14 and abs(bt["t_PO"] - 2.0) < 1e-14 and abs(bt["t_sqz"] - 2.0) < 1e-14
+
+
+def test_derive_principal_mode_on_a_site_kerr_state():
+    """fh_derive's V_- of the principal mode on the pinned state of S3: a
+    contact interaction with one occupied site mode b_1 (M = 4), evolved
+    exactly.  fh_derive takes the oracle's unnormalised moments and must
+    return the single-mode Kerr V_- (xi, not conj(xi)), the normalised
+    moments and the mode occupations n_k = <a_k^+ a_k>/<psi|psi>."""
+    import math
+
+    import paper_2111_00050_amd as fh
+    import workloads as W
+    from oracle import Oracle, derived, states
+
+    from test_oracle_pins import _expm_by_sector, _kerr_moments, _single_mode_vminus
+
+    M, Lam, x, Nmax = 4, 0.3, 1, 17
+    F = np.exp(2j * np.pi * np.outer(np.arange(M), np.arange(M)) / M) / math.sqrt(M)
+    beta = np.zeros(M, np.complex128)
+    beta[x] = np.exp(0.7j)
+    o = Oracle(M, M, np.zeros(M), Lam, W.V_contact(M), W.all_sectors(M, Nmax))
+    psi0 = states.coherent_state(o, F.conj().T @ beta)
+    for t in (0.25, 1.2):
+        psi = 1.7 * _expm_by_sector(o, psi0, t)  # unnormalised on purpose
+        n2, a, Mij, A = o.moments(psi)
+        g = fh.derive(M, n2, a, Mij, A)
+        want = _single_mode_vminus(*_kerr_moments(beta[x], Lam * M, t))
+        assert abs(g["vminus"] - want) <= 1e-10
+        od = derived.derive(n2, a, Mij, A)
+        np.testing.assert_allclose(g["a"], od["a"], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(g["M"], od["M"], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(g["A"], od["A"], rtol=0, atol=1e-14)
+        np.testing.assert_allclose(g["n_modes"], np.real(np.diag(Mij)) / n2, rtol=0, atol=1e-14)
+        assert abs(np.sum(g["n_modes"]) - g["n_tot"]) <= 1e-13
+    # a zero norm gives NaN everywhere and FH_ESTATE (mapped to NaN, no raise)
+    z = np.zeros(M, np.complex128)
+    g = fh.derive(M, 0.0, z, np.zeros((M, M), np.complex128), np.zeros((M, M), np.complex128))
+    assert np.isnan(g["n_tot"]) and np.all(np.isnan(g["n_modes"])) and np.all(np.isnan(g["M"]))

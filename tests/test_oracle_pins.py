@@ -22,6 +22,12 @@ identity, a dense-matrix propagator, a printed number of the paper).
       dense propagator, second order only with c2 = 1/2
   X1-X2 Chebyshev propagator: equal to exp(-i H t) (dense expm) and to the
       free phases exp(-i E t), at steps where RK4 is unstable
+  E1-E2 the paper's exact interactions (Eq. Lambda) and their embedding in
+      periodic sectors
+  S1-S2 single-mode squeezing: the large-n approximation and the early slope
+  S3  V_- of the principal mode (Eq. generalVminus, Eq. a_op) for M > 1 where
+      the state is one Kerr-evolved site mode (catches xi <-> conj(xi))
+  S4  per-mode V_- against Kerr closed forms (M = 1; one Kerr mode of M = 4)
 """
 import itertools
 import math
@@ -619,3 +625,111 @@ def test_s2_early_time_squeezing_slope(oracle_lib):
     assert 1.7 <= (1.0 - slope[1]) / (1.0 - slope[0]) <= 2.3
     a, b = _kerr_vminus(50.0, [0.05, 0.06])
     assert a > 0.8 > b
+
+
+# ------------------------------------------------------------------ S3-S4 --
+# Squeezing of a principal mode (Sec. II.E, Eq. generalVminus with the mode of
+# Eq. a_op) and of single modes, pinned where the many-mode dynamics reduce to
+# one Kerr oscillator whose moments are known in closed form.
+
+def _expm_by_sector(o, psi0, t):
+    """exp(-i H t) psi0 with a dense eigendecomposition of each retained sector
+    on its own (H never couples sectors, Sec. III.B)."""
+    out = np.empty_like(psi0)
+    for s, sec in enumerate(o.sectors):
+        lo, d = o.offsets[s], o.dims[s]
+        if d == 0:
+            continue
+        one = Oracle(o.M, o.pmod, o.omega, o.Lambda, o.V, [sec])
+        out[lo:lo + d] = dense.expm_evolve(dense.dense_h(one), psi0[lo:lo + d], t)
+    return out
+
+
+def _kerr_moments(z, g, t, w=0.0):
+    """<b>, <b^2>, <b^+ b> of a coherent state |z> at time t under
+    H = w b^+ b + (g/2) b^+ b^+ b b (a rotation times the single-mode Kerr
+    evolution of P6)."""
+    n = abs(z) ** 2
+    m1 = z * np.exp(-1j * w * t) * np.exp(n * (np.exp(-1j * g * t) - 1))
+    m2 = z * z * np.exp(-2j * w * t) * np.exp(-1j * g * t) * np.exp(n * (np.exp(-2j * g * t) - 1))
+    return m1, m2, n
+
+
+def _single_mode_vminus(m1, m2, n):
+    """Eq. (generalVminus) for one mode with <O> = m1, <O^2> = m2, <O^+ O> = n."""
+    return 1.0 + 2.0 * (n - abs(m1) ** 2) - 2.0 * abs(m2 - m1 * m1)
+
+
+def _principal_vminus(d, conj_xi=False):
+    """V_- of O = sum_k c_k a_k with c = xi (or, as a planted mistake, conj(xi))
+    from the oracle's normalised moments and principal eigenvector."""
+    c = np.conj(d["xi"]) if conj_xi else d["xi"]
+    O = complex(np.sum(c * d["a"]))
+    OdO = float(np.real(np.conj(c) @ d["M"] @ c))
+    O2 = complex(c @ d["A"] @ c)
+    return _single_mode_vminus(O, O2, OdO)
+
+
+@pytest.mark.parametrize("M,r,Nmax", [(3, 1.0, 18), (4, 1.0, 17), (5, 0.6, 11)])
+def test_s3_principal_mode_vminus_is_the_site_kerr_oscillator(oracle_lib, M, r, Nmax):
+    """Contact interaction, w = 0, and a coherent state with a single occupied
+    site mode b_x (x = 1, beta_x = e^{0.7 i}; alpha = F^+ beta has complex
+    components).  By P5 the state stays a Kerr-evolved coherent state of b_x
+    with rate Lambda M and vacuum in every other b mode, so M_ij has the single
+    nonzero eigenvalue |beta_x|^2, the principal mode of Eq. (a_op) is b_x, and
+    V_- must equal the single-mode Kerr value at every time.  With conj(xi) the
+    operator would be b_{-x}, a vacuum mode (V_- = 1): the pin tells the two
+    apart.  |beta_x| = r; the Poisson(r^2) tail beyond Nmax, weighted by n^2
+    (it enters <b^2>), stays below 1e-12."""
+    Lam, x = 0.3, 1
+    F = np.exp(2j * np.pi * np.outer(np.arange(M), np.arange(M)) / M) / math.sqrt(M)  # b = F a
+    beta = np.zeros(M, np.complex128)
+    beta[x] = r * np.exp(0.7j)
+    alpha = F.conj().T @ beta
+    assert np.max(np.abs(alpha.imag)) > 0.1
+    o = Oracle(M, M, np.zeros(M), Lam, W.V_contact(M), W.all_sectors(M, Nmax))
+    psi0 = states.coherent_state(o, alpha)
+    for t in (0.25, 1.2, 1.9):
+        d = derived.observe(o, _expm_by_sector(o, psi0, t))
+        m1, m2, n = _kerr_moments(beta[x], Lam * M, t)
+        want = _single_mode_vminus(m1, m2, n)
+        assert abs(d["lambda_p"] - n) <= 1e-10
+        assert abs(d["vminus"] - want) <= 1e-10, (M, t, d["vminus"], want)
+        assert abs(1.0 - want) > 0.05               # the pin is not the vacuum value 1
+        assert abs(_principal_vminus(d) - want) <= 1e-10
+        assert abs(_principal_vminus(d, conj_xi=True) - want) > 0.05
+        assert abs(_principal_vminus(d, conj_xi=True) - 1.0) <= 1e-10
+
+
+def test_s4_per_mode_vminus_kerr_closed_forms(oracle_lib):
+    """Per-mode V_- (Eq. generalVminus with O = a_i) where single modes are
+    exact Kerr oscillators: (a) M = 1 against the closed form; (b) M = 4 with
+    the interaction V[k,k,k,k] on mode k = 2 only and nonzero frequencies, so
+    mode 2 is a rotating Kerr oscillator (rate Lambda V_kkkk) and the other modes
+    rotate freely and stay unsqueezed (V_- = 1)."""
+    # (a) one mode
+    Lam, z, Nmax = 0.2, 1.1 * np.exp(0.4j), 30
+    o1 = Oracle(1, 1, np.zeros(1), Lam, np.ones((1, 1, 1, 1)), [(n, 0) for n in range(Nmax + 1)])
+    psi0 = states.coherent_state(o1, [z])
+    for t in (0.3, 1.2, 4.0):
+        d = derived.observe(o1, _expm_by_sector(o1, psi0, t))
+        want = _single_mode_vminus(*_kerr_moments(z, Lam, t))
+        assert abs(d["vminus_mode"][0] - want) <= 1e-10
+        assert abs(1.0 - want) > 0.05
+    # (b) one Kerr mode among free ones
+    M, k, Vk, Nmax = 4, 2, 1.5, 20
+    omega = np.array([0.3, -0.2, 0.5, 0.1])
+    V = np.zeros((M,) * 4)
+    V[k, k, k, k] = Vk
+    alpha = np.array([0.5, 0.4j, 0.9 * np.exp(0.3j), 0.3])
+    o = Oracle(M, M, omega, Lam, V, W.all_sectors(M, Nmax))
+    psi0 = states.coherent_state(o, alpha)
+    for t in (0.5, 2.5):
+        d = derived.observe(o, _expm_by_sector(o, psi0, t))
+        m1, m2, n = _kerr_moments(alpha[k], Lam * Vk, t, omega[k])
+        assert abs(d["a"][k] - m1) <= 1e-10 and abs(d["A"][k, k] - m2) <= 1e-10
+        want = _single_mode_vminus(m1, m2, n)
+        assert abs(d["vminus_mode"][k] - want) <= 1e-10
+        assert abs(1.0 - want) > 0.02
+        others = [i for i in range(M) if i != k]
+        np.testing.assert_allclose(d["vminus_mode"][others], 1.0, rtol=0, atol=1e-10)
