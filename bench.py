@@ -25,6 +25,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# Vector-memory (texture) path: 256 CUs, 64 B per clock each into the vector
+# L1, 2.4 GHz.  A 64-lane b128 gather (16 B per lane) occupies it for 16
+# clocks, so this is also the gather-issue ceiling of the stage kernel.
+CU_COUNT, CLOCK_GHZ, L1_BYTES_PER_CLK = 256, 2.4, 64
+PEAK_GATHER_GBS = CU_COUNT * L1_BYTES_PER_CLK * CLOCK_GHZ
 # Algorithmic bytes per state of the four fused stages (complex128 = 16 B):
 #   stage 1: read psi, write acc and y2               = 48
 #   stage 2: read y2, psi, acc; write acc and y3      = 80
@@ -90,6 +95,70 @@ def _oracle_rows_worker(job):
     return nrows, time.perf_counter() - t0
 
 
+def gathers_per_row(M: int) -> int:
+    """Neighbour gathers the stage kernel issues per row: for each momentum
+    class c of unordered pairs {i <= j} (class (i + j) mod M) with S_c pairs,
+    S_c (S_c - 1) ordered (row pair, source pair) combinations."""
+    cls = [0] * M
+    for i in range(M):
+        for j in range(i, M):
+            cls[(i + j) % M] += 1
+    return sum(c * (c - 1) for c in cls)
+
+
+def apply_timing(fh, torch, model, basis, x, warmup=3, runs=20):
+    """Median duration (s) of one H psi launch (fh_apply_h, APPLY mode) from
+    HIP events recorded on the launch stream around each call."""
+    out = torch.empty_like(x)
+    for _ in range(warmup):
+        fh.apply_h(model, basis, x, out)
+    ts = []
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fh.apply_h(model, basis, x, out)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def copy_bandwidth(torch, nbytes=1 << 31, runs=10):
+    """Device-to-device copy rate (read + write bytes / s, median of runs): the
+    practical HBM peak on this GPU."""
+    n = nbytes // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ts = []
+    for _ in range(runs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) / 1e3)
+    ts.sort()
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / ts[len(ts) // 2] / 1e9
+
+
+def host_info() -> dict:
+    """nproc and the CPU model of this host (for the CPU-baseline line)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
 def cpu_workers() -> int:
     """Host cores for the CPU baseline: the process's CPU set, at most 16 (a
     one-GPU share of the host)."""
@@ -128,7 +197,7 @@ def cpu_baseline(w, target_s: float = 10.0):
     del orc, psi
     cores = cpu_workers()
     if cores == 1:
-        return {"value": one, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle",
+        return {"value": one, "unit": "RK4 steps/s", "cores": 1, "kind": "oracle", **host_info(),
                 "sample": f"oracle gather-form H psi on {n} random rows of the {D}-state sector ({dt1:.1f} s), "
                           f"scaled to 4 H psi per RK4 step"}
     with mp.get_context("spawn").Pool(cores) as pool:
@@ -140,6 +209,8 @@ def cpu_baseline(w, target_s: float = 10.0):
         "unit": "RK4 steps/s",
         "cores": cores,
         "kind": "oracle",
+        **host_info(),
+        "one_thread_value": one,
         "sample": f"oracle gather-form H psi, {cores} processes on independently seeded samples of {n} random rows of "
                   f"the {D}-state sector each ({wall:.1f} s of parallel time), scaled to 4 H psi per RK4 step; "
                   f"one thread: {one:.3g} steps/s",
@@ -416,9 +487,13 @@ def main():
     if args.warmup > 0:
         fh.evolve_rk4(model, basis, psi, w.dt, args.warmup, work=work)
     torch.cuda.synchronize()
+    # moments every 50 steps as the workload asks; when the timed steps are not
+    # a multiple of that, at the first and the last timed step instead, so that
+    # the drift checks always compare two states
+    every = w.every if args.steps % w.every == 0 else args.steps
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
-    res = fh.evolve_rk4(model, basis, psi, w.dt, args.steps, every=w.every, flags=fh.FH_TIMING, work=work)
+    res = fh.evolve_rk4(model, basis, psi, w.dt, args.steps, every=every, flags=fh.FH_TIMING, work=work)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     steps_per_s = args.steps / elapsed
@@ -429,6 +504,13 @@ def main():
     norms = res.records[:, 0, 0]
     obs0 = fh.derive(w.M, *fh.unpack_moments(w.M, res.records[0, 0]))
     obsT = fh.derive(w.M, *fh.unpack_moments(w.M, res.records[-1, 0]))
+    # after the timed region: H psi launches timed on their own, and the
+    # device's copy bandwidth (the practical peak)
+    print("[bench] timing H psi launches and a device copy", file=sys.stderr, flush=True)
+    apply_s = apply_timing(fh, torch, model, basis, psi)
+    copy_gbs = copy_bandwidth(torch)
+    gpr = gathers_per_row(w.M)
+    gather_gbs = gpr * 16.0 * D / avg_stage_s / 1e9
     line = {
         "metric": "RK4 Fock steps/s",
         "value": steps_per_s,
@@ -448,7 +530,10 @@ def main():
             "states": D,
             "parallelism": "single GPU",
         },
-        "hpsi_per_s": 4.0 * steps_per_s,
+        "hpsi_per_s": 1.0 / apply_s,
+        "hpsi_ms": 1e3 * apply_s,
+        "hpsi_timing": "median of 20 fh_apply_h launches (APPLY mode, 3 warm-up) between HIP events on the launch "
+                       "stream, after the timed steps",
         "launch": launch,
         "stage_kernel_ms": 1e3 * avg_stage_s,
         "roofline": {
@@ -458,8 +543,26 @@ def main():
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBS,
             "traffic": traffic,
+            "bytes_model": f"{STAGE_BYTES_PER_STATE:.0f} B per state per stage launch (mean over the four fused "
+                           "stages: 48, 80, 80, 48 B; every vector once, the gathered vector once)",
+            "practical_peak": copy_gbs,
+            "frac_of_practical_peak": achieved / copy_gbs,
+            "traffic_frac": (None if traffic is None else traffic / avg_stage_s / 1e9 / PEAK_HBM_GBS),
+            "binding_unit": "vector-memory gather path (texture addresser / L1, waiting on L2 misses); see "
+                            "roofline_gather",
+        },
+        "roofline_gather": {
+            "bound": "vector-memory gather issue",
+            "gathers_per_row": gpr,
+            "achieved": gather_gbs,
+            "peak": PEAK_GATHER_GBS,
+            "unit": "GB/s",
+            "frac": gather_gbs / PEAK_GATHER_GBS,
+            "model": f"{gpr} b128 neighbour gathers (16 B per lane) per row per stage launch; peak {CU_COUNT} CUs x "
+                     f"{L1_BYTES_PER_CLK} B/clock x {CLOCK_GHZ} GHz into the vector L1",
         },
         "checks": {
+            "records_at_steps": [int(x) for x in res.steps],
             "norm_drift": float(abs(norms[-1] - norms[0])),
             "n_tot_drift": float(abs(obsT["n_tot"] - obs0["n_tot"])),
             "lambda_p_end": obsT["lambda_p"],

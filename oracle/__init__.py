@@ -97,8 +97,12 @@ class Oracle:
     the sectors in the order given.
     """
 
-    def __init__(self, M, pmod, omega, Lambda, V, sectors):
+    def __init__(self, M, pmod, omega, Lambda, V, sectors, threads=1):
         self.M, self.pmod = int(M), int(pmod)
+        # threads > 1: apply_h runs the gather form (apply_h_rows) on row
+        # blocks in that many threads (the C call releases the GIL); the result
+        # equals the scatter form up to summation order (pin P3).
+        self.threads = max(1, int(threads))
         self.omega = np.ascontiguousarray(omega, dtype=np.float64).reshape(M)
         self.Lambda = float(Lambda)
         self.V = np.ascontiguousarray(V, dtype=np.float64).reshape(M, M, M, M)
@@ -150,8 +154,28 @@ class Oracle:
     def apply_h(self, psi: np.ndarray) -> np.ndarray:
         psi = np.ascontiguousarray(psi, dtype=np.complex128)
         assert psi.shape == (self.total,)
+        if self.threads > 1 and self.total >= 4096:
+            return self._apply_h_threads(psi)
         out = np.empty_like(psi)
         self._lib.ora_apply_h(self._h, _ptr(psi), _ptr(out))
+        return out
+
+    def _apply_h_threads(self, psi: np.ndarray) -> np.ndarray:
+        from concurrent.futures import ThreadPoolExecutor
+
+        rows = np.arange(self.total, dtype=np.int64)
+        out = np.empty_like(psi)
+        blocks = np.array_split(np.arange(self.total), 4 * self.threads)
+
+        def run(b):
+            if len(b):
+                o = np.empty(len(b), np.complex128)
+                r = np.ascontiguousarray(rows[b[0]:b[-1] + 1])
+                self._lib.ora_apply_h_rows(self._h, _ptr(psi), len(r), _ptr(r), _ptr(o))
+                out[b[0]:b[-1] + 1] = o
+
+        with ThreadPoolExecutor(self.threads) as ex:
+            list(ex.map(run, blocks))
         return out
 
     def apply_h_rows(self, psi: np.ndarray, rows) -> np.ndarray:
@@ -203,4 +227,4 @@ class Oracle:
         (a_i^+ a_j^+ a_k a_l)^+ = a_k^+ a_l^+ a_i a_j, so H^+ has V'[i,j,k,l] = V[k,l,i,j].
         """
         return Oracle(self.M, self.pmod, self.omega, self.Lambda,
-                      self.V.transpose(2, 3, 0, 1), self.sectors)
+                      self.V.transpose(2, 3, 0, 1), self.sectors, self.threads)

@@ -526,12 +526,27 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
     return FH_OK;
 }
 
-// Moments of one rhs into host doubles [norm2, a(2M), M(2M^2), A(2M^2)].
-fh_status run_moments(const fh_basis* b, int nrhs, int rhs, const double* psi, double* rec, hipStream_t s,
-                      int groups) {
+}  // namespace
+
+namespace fh {
+// Workgroups of the moments launch for this basis and its dynamic LDS bytes.
+int moments_grid(const fh_basis* b, size_t* lds) {
+    const int NO = momentsOut(b->M);
+    *lds = lds_bytes(b, 4 * 2 * NO);
+    const int nt = (int)b->tiles.size();
+    return nt > 0 ? persistent_grid(b, b->ks->moments_fn, *lds, nt) : 0;
+}
+
+// Moments of one rhs into host doubles rec = [norm2, a(2M), M(2M^2), A(2M^2)].
+// Scratch: partial holds groups * G * 2 * kMomOutMax doubles (G = moments_grid),
+// reduced groups * 2 * momentsOut(M) doubles (device); v is host staging of
+// groups * 2 * momentsOut(M) doubles.  Every scratch word read is written first.
+fh_status moments_core(const fh_basis* b, int nrhs, int rhs, const double* psi, double* rec, hipStream_t s,
+                       int groups, double* partial, double* reduced, double* v) {
     const int M = b->M, NO = momentsOut(M);
     const int nt = (int)b->tiles.size();
-    const size_t lds = lds_bytes(b, 4 * 2 * NO);
+    size_t lds = 0;
+    const int G = moments_grid(b, &lds);
     MomArgs a{};
     a.psi = psi;
     a.nrhs = nrhs;
@@ -546,17 +561,17 @@ fh_status run_moments(const fh_basis* b, int nrhs, int rhs, const double* psi, d
     a.secs = b->d_secs;
     a.secmap = b->d_secmap;
     a.Nmax = b->Nmax;
-    a.partial = b->d_partial;
+    a.partial = partial;
     a.xcd_order = b->xcd_order;
     a.occ = b->d_occ;
-    std::vector<double> v((size_t)groups * 2 * NO, 0.0);
+    const size_t nv = (size_t)groups * 2 * NO;
+    std::fill(v, v + nv, 0.0);
     if (nt > 0) {
-        const int G = persistent_grid(b, b->ks->moments_fn, lds, nt);
         b->ks->moments(a, G, groups, lds, s);
         FH_HIP(hipGetLastError());
-        launch_reduce_partials(b->d_partial, groups, G, 2 * kMomOutMax, 2 * NO, b->d_small, 0, s);
+        launch_reduce_partials(partial, groups, G, 2 * kMomOutMax, 2 * NO, reduced, 0, s);
         FH_HIP(hipGetLastError());
-        FH_HIP(hipMemcpyAsync(v.data(), b->d_small, sizeof(double) * v.size(), hipMemcpyDeviceToHost, s));
+        FH_HIP(hipMemcpyAsync(v, reduced, sizeof(double) * nv, hipMemcpyDeviceToHost, s));
         FH_HIP(hipStreamSynchronize(s));
     }
     const size_t need = FH_MOMENT_DOUBLES(M);
@@ -588,6 +603,16 @@ fh_status run_moments(const fh_basis* b, int nrhs, int rhs, const double* psi, d
         }
     }
     return FH_OK;
+}
+}  // namespace fh
+
+namespace {
+
+// Moments of one rhs with the basis's own scratch.
+fh_status run_moments(const fh_basis* b, int nrhs, int rhs, const double* psi, double* rec, hipStream_t s,
+                      int groups) {
+    std::vector<double> v((size_t)groups * 2 * momentsOut(b->M));
+    return moments_core(b, nrhs, rhs, psi, rec, s, groups, b->d_partial, b->d_small, v.data());
 }
 
 fh_status init_product(const fh_basis* b, int nrhs, const std::vector<double>& tab, double* psi, hipStream_t s) {

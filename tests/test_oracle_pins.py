@@ -115,6 +115,19 @@ def test_p3_scatter_equals_gather(oracle_lib):
         np.testing.assert_allclose(o.apply_h_rows(x, rows), full, rtol=0, atol=1e-12 * np.abs(full).max())
 
 
+def test_p3_threaded_gather_equals_scatter(oracle_lib):
+    """The oracle's threaded gather apply (row blocks in parallel) equals its
+    scatter form on a multi-sector basis of an M = 8 long-range model."""
+    M = 8
+    secs = [(10, 0), (9, 3), (8, 5)]
+    o1 = Oracle(M, M, W.omega_quadratic(M), 0.02, W.V_longrange(M), secs)
+    o4 = Oracle(M, M, W.omega_quadratic(M), 0.02, W.V_longrange(M), secs, threads=4)
+    assert o1.total >= 4096
+    x = W.random_psi(o1.total, 8)
+    full = o1.apply_h(x)
+    np.testing.assert_allclose(o4.apply_h(x), full, rtol=0, atol=1e-12 * np.abs(full).max())
+
+
 def test_p3_nonsymmetric_v_transpose(oracle_lib):
     """H(V[k,l,i,j]) is the transpose of H(V): <x, H y> = <H' x, y> for real x-conjugation."""
     o = _small_model(sym=False)
