@@ -142,6 +142,23 @@ fh_status fh_apply_h(const fh_model* m, const fh_basis* b, int nrhs, const fh_c6
 fh_status fh_moments(const fh_basis* b, int nrhs, int rhs, const fh_c64* psi, double* norm2,
                      fh_c64* a, fh_c64* Mij, fh_c64* Akl, void* stream);
 
+/* Allocation-free variant of fh_moments, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, same results (bitwise: same launch grid
+ * and summation order); the per-workgroup partial sums and the reduced values
+ * live in a static device array of 2^20 doubles (8 MiB) that every GPU the
+ * library runs on holds until the process ends, instead of the basis's
+ * scratch.  The call allocates nothing (no hipMalloc, hipFree or other
+ * allocating routine; host staging is on the stack).  Every call on one GPU
+ * shares that array and overwrites it, so calls that overlap on one GPU race
+ * (and so do calls on different streams); every word read is written first
+ * by the same call, so nothing needs clearing.  FH_EUNSUPPORTED if the
+ * reduction of this basis on this device needs more than 2^20 doubles
+ * ((M + 1) * workgroups * 42 + (M + 1) * 2 * (2M + 1); MI355X: at most
+ * 946,638); FH_EINVAL if the basis was created on another device. */
+fh_status fh_moments_noalloc(const fh_basis* b, int nrhs, int rhs, const fh_c64* psi, double* norm2,
+                             fh_c64* a, fh_c64* Mij, fh_c64* Akl, void* stream);
+
 typedef struct {
     double norm2;      /* <psi|psi> */
     double n_tot;      /* sum_i <a_i^+ a_i> / norm2 */

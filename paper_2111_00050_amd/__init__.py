@@ -69,6 +69,7 @@ SIGNATURES = {
     "fh_init_fieldnumber": (_I, [_P, _P, _I, _P, _P]),
     "fh_apply_h": (_I, [_P, _P, _I, _P, _P, _P]),
     "fh_moments": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
+    "fh_moments_noalloc": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P]),
     "fh_derive": (_I, [_I, _D, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     "fh_first_crossing": (_I, [_P, _P, _I64, _D, _I, _P]),
     "fh_evolve_rk4": (_I, [_P, _P, _I, _P, _P, _D, _I64, _I64, _P, _I64, _I, _P, _P]),
@@ -311,6 +312,21 @@ def moments(basis, psi, rhs=0):
     Akl = np.zeros((M, M), np.complex128)
     _check(_lib.fh_moments(basis.handle, nrhs, int(rhs), _dev_ptr(psi, torch.complex128, "psi"), _np_ptr(n2),
                            _np_ptr(a), _np_ptr(Mij), _np_ptr(Akl), _stream()))
+    return float(n2[0]), a, Mij, Akl
+
+
+def moments_noalloc(basis, psi, rhs=0):
+    """fh_moments_noalloc: the same moments as moments(), with the reduction
+    scratch in the library's static device array (no allocation)."""
+    torch = _torch()
+    nrhs = _nrhs_of(basis, psi)
+    M = basis.M
+    n2 = np.zeros(1)
+    a = np.zeros(M, np.complex128)
+    Mij = np.zeros((M, M), np.complex128)
+    Akl = np.zeros((M, M), np.complex128)
+    _check(_lib.fh_moments_noalloc(basis.handle, nrhs, int(rhs), _dev_ptr(psi, torch.complex128, "psi"), _np_ptr(n2),
+                                   _np_ptr(a), _np_ptr(Mij), _np_ptr(Akl), _stream()))
     return float(n2[0]), a, Mij, Akl
 
 

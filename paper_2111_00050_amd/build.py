@@ -55,7 +55,7 @@ def _units():
                           [f"-DFH_INST_M={m}", f"-DFH_INST_R={r}"], m ** 3 * (1 + r / 4)))
         units.append((os.path.join(CSRC, "inst_aux.hip"), os.path.join(OBJ, f"aux_M{m}.o"),
                       [f"-DFH_INST_M={m}"], m ** 3))
-    for f in ("util.hip", "api.hip", "derive.cpp"):
+    for f in ("util.hip", "api.hip", "noalloc.hip", "derive.cpp"):
         src = os.path.join(CSRC, f)
         extra = ["-x", "hip"] if f.endswith(".cpp") else []
         units.append((src, os.path.join(OBJ, os.path.splitext(f)[0] + ".o"), extra, 1))
