@@ -95,6 +95,23 @@ def _oracle_rows_worker(job):
     return nrows, time.perf_counter() - t0
 
 
+def adjoint_checkpoints(torch, nsteps: int, vec_bytes: int, frac: float = 0.8):
+    """Checkpoint interval for fh_adjoint_rk4 that uses the free device memory:
+    the largest C <= nsteps whose work buffer with kept stage inputs (segments +
+    4C + 10 state vectors) fits in frac of what is free; else the largest C
+    with recomputed stage inputs (segments + C + 10).  Returns (C, kept)."""
+    torch.cuda.empty_cache()  # blocks cached by torch count as free here
+    free, _ = torch.cuda.mem_get_info()
+    budget = frac * free
+    for kept in (True, False):
+        for C in range(nsteps, 0, -1):
+            nseg = -(-nsteps // C)
+            vecs = nseg + (4 * C if kept else C) + 10
+            if vecs * vec_bytes <= budget:
+                return C, kept
+    return 1, False
+
+
 def gathers_per_row(M: int) -> int:
     """Neighbour gathers the stage kernel issues per row: for each momentum
     class c of unordered pairs {i <= j} (class (i + j) mod M) with S_c pairs,
@@ -379,43 +396,75 @@ def forms():
 
     # ---- adjoint vs forward
     adj = []
-    for w, obj, steps, ck in ((W.adjoint_number(30), fh.FH_J_NMODE, 3000, 100),
-                              (W.adjoint_coherent(20.0), fh.FH_J_Q, 100, 10),
-                              (W.fieldnumber_draws(16, 30), fh.FH_J_PO, 10, 5)):
+    for w, obj, steps, nd in ((W.adjoint_number(30), fh.FH_J_NMODE, 3000, 1),
+                              (W.adjoint_coherent(20.0), fh.FH_J_Q, 100, 1),
+                              (W.fieldnumber_draws(16, 30), fh.FH_J_PO, 10, 1),
+                              (W.fieldnumber_draws(16, 30), fh.FH_J_PO, 10, 2)):
         model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
-        log(f"adjoint: {w.name}, {basis.total} states, {steps} steps")
+        log(f"adjoint: {w.name}, {basis.total} states x {nd}, {steps} steps")
 
-        def init(b=basis, w=w):
+        def init(b=basis, w=w, nd=nd):
             if w.init == "number":
                 return fh.init_number(b, w.init_params)
             if w.init == "fieldnumber":
-                return fh.init_fieldnumber(b, w.init_params[0])  # one phase draw
+                return fh.init_fieldnumber(b, w.init_params[0] if nd == 1 else w.init_params[:nd])
             return fh.init_coherent(b, w.init_params)
 
+        ck, keep = adjoint_checkpoints(torch, steps, 16 * basis.total * nd)
+        # work buffers are allocated outside the timed calls (both sides)
         psi = init()
-        _, tf = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps))
+        fwork = torch.empty(3 * basis.total * nd, dtype=c128, device="cuda")
+        _, tf = timed(lambda: fh.evolve_rk4(model, basis, psi, w.dt, steps, work=fwork))
+        del psi, fwork
         psi0 = init()
-        res, ta = timed(lambda: fh.adjoint_rk4(model, basis, psi0, w.dt, steps, ck, obj, 0))
-        name = w.name + (", draw 0 only" if w.init == "fieldnumber" else "")
-        tan, tt = timed(lambda: fh.tangent_rk4(model, basis, psi0, w.dt, steps, obj, 0))
-        del tan["psi"], tan["dpsi"]
-        rec = {"workload": name, "states": basis.total, "steps": steps, "checkpoint_every": ck,
+        size_fn = fh._lib.fh_adjoint_work_states_kept if keep else fh._lib.fh_adjoint_work_states
+        awork = torch.empty(int(size_fn(steps, ck)) * basis.total * nd, dtype=c128, device="cuda")
+        res, ta = timed(lambda: fh.adjoint_rk4(model, basis, psi0, w.dt, steps, ck, obj, 0, work=awork))
+        name = w.name + ((", draw 0 only" if nd == 1 else f", draws 0..{nd - 1} in one vector")
+                         if w.init == "fieldnumber" else "")
+        rec = {"workload": name, "states": basis.total, "columns": nd, "steps": steps, "checkpoint_every": ck,
+               "stage_inputs_kept": keep,
                "objective": {fh.FH_J_Q: "Q", fh.FH_J_NMODE: "<n_0>(T)", fh.FH_J_PO: "1 - lambda_p/n_tot"}[obj],
                "forward_s": tf, "adjoint_s": ta, "ratio": ta / tf,
-               "J": float(res["J"][0]), "dJ_dLambda": float(res["dLambda"][0]),
-               "tangent_s": tt, "tangent_ratio": tt / tf, "tangent_dJ_dLambda": float(tan["dLambda"][0])}
+               "J": [float(x) for x in res["J"]], "dJ_dLambda": [float(x) for x in res["dLambda"]]}
+        if nd > 1:
+            # per-draw time against the same draws adjointed one at a time
+            lam_both = res["lambda0"]
+            res1, ta1 = None, 0.0
+            diffs = []
+            del awork
+            ck1, keep1 = adjoint_checkpoints(torch, steps, 16 * basis.total)
+            size_fn = fh._lib.fh_adjoint_work_states_kept if keep1 else fh._lib.fh_adjoint_work_states
+            awork = torch.empty(int(size_fn(steps, ck1)) * basis.total, dtype=c128, device="cuda")
+            for q in range(nd):
+                p1 = fh.init_fieldnumber(basis, w.init_params[q])
+                r1, t1 = timed(lambda: fh.adjoint_rk4(model, basis, p1, w.dt, steps, ck1, obj, 0, work=awork))
+                ta1 += t1
+                diffs.append(max(abs(float(r1["dLambda"][0]) - float(res["dLambda"][q])),
+                                 float(np.abs(r1["dV"][0] - res["dV"][q]).max()),
+                                 float((r1["lambda0"][:, 0] if r1["lambda0"].dim() > 1 else r1["lambda0"]).sub(
+                                     lam_both[:, q]).abs().max())))
+                del p1, r1
+            rec.update({"one_at_a_time_checkpoint_every": ck1, "one_at_a_time_adjoint_s": ta1,
+                        "per_draw_s": ta / nd, "per_draw_one_at_a_time_s": ta1 / nd,
+                        "speedup_over_one_at_a_time": ta1 / ta, "max_abs_diff_vs_one_at_a_time": max(diffs)})
+            del lam_both
+        else:
+            tan, tt = timed(lambda: fh.tangent_rk4(model, basis, psi0, w.dt, steps, obj, 0))
+            del tan["psi"], tan["dpsi"]
+            rec.update({"tangent_s": tt, "tangent_ratio": tt / tf, "tangent_dJ_dLambda": float(tan["dLambda"][0])})
         if steps == 3000:
             h = 1e-6
             Jpm = []
             for sgn in (1, -1):
                 mh = fh.Model(w.M, w.omega, w.Lambda + sgn * h, w.V)
-                Jpm.append(float(fh.adjoint_rk4(mh, basis, init(), w.dt, steps, ck, obj, 0)["J"][0]))
+                Jpm.append(float(fh.adjoint_rk4(mh, basis, init(), w.dt, steps, ck, obj, 0, work=awork)["J"][0]))
                 mh.close()
             fd = (Jpm[0] - Jpm[1]) / (2 * h)
             rec["dJ_dLambda_central_difference"] = fd
-        log(f"  adjoint ratio {ta / tf:.2f}, tangent ratio {tt / tf:.2f}")
+        log(f"  adjoint ratio {ta / tf:.2f} (checkpoint every {ck}, kept {keep})")
         adj.append(rec)
-        del psi, psi0, res
+        del psi0, res, awork
         model.close()
         basis.close()
         torch.cuda.empty_cache()

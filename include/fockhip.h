@@ -243,7 +243,8 @@ fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c
  * workgroups per compute unit (0 = occupancy limit) and the XCD-aware tile
  * order (0 = plain round robin, 1 = the XCDs take contiguous chunks of tiles
  * in turn, 2 = each XCD walks one contiguous eighth of the tile list).
- * Not thread-safe with concurrent calls on the same basis. */
+ * A new basis starts at (0, 2).  Not thread-safe with concurrent calls on
+ * the same basis. */
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
 /* Tiling and schedule of each sector's rows; storage stays lexicographic and
  * results do not depend on it.  Tiles (<= 256 consecutive rows) never cross a

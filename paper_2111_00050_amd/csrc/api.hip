@@ -1478,12 +1478,25 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         };
 
         // ---- forward sweep storing checkpoints (the running state is the
-        //      first segment slot)
+        //      first segment slot).  With kept stage inputs, the last segment
+        //      (the first one reversed) keeps its states and stage inputs
+        //      here, so that the reverse sweep need not recompute it.
         double* run = segst(0);
         FH_HIP(hipMemcpyAsync(buf(0), psi0, vbytes, hipMemcpyDeviceToDevice, s));
         FH_HIP(hipMemcpyAsync(run, psi0, vbytes, hipMemcpyDeviceToDevice, s));
         for (int64_t k = 0; k < nseg; ++k) {
             const int64_t len = std::min(C, nsteps - k * C);
+            if (keep && k == nseg - 1) {
+                // state(0) is the checkpoint buf(k) (== run); states 1..len-1 go to
+                // the segment slots, psi_T to run
+                for (int64_t t = 0; t < len; ++t) {
+                    const double* from = t == 0 ? buf(k) : segst(t);
+                    double* to = t + 1 < len ? segst(t + 1) : run;
+                    st = step(from, to, kept(1, t), kept(2, t), kept(3, t), 4);
+                    if (st != FH_OK) return st;
+                }
+                break;
+            }
             for (int64_t t = 0; t < len; ++t) {
                 st = step(run, run, yA, yB, yA, 4);
                 if (st != FH_OK) return st;
@@ -1524,12 +1537,14 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
             const int64_t len = std::min(C, nsteps - k * C);
             // state of step t of the segment: the checkpoint itself for t = 0
             auto state = [&](int64_t t) { return t == 0 ? buf(k) : segst(t); };
-            for (int64_t t = 1; t < len; ++t) {
+            // the last segment's states and stage inputs are already there
+            const bool have = keep && k == nseg - 1;
+            for (int64_t t = 1; t < len && !have; ++t) {
                 st = keep ? step(state(t - 1), state(t), kept(1, t - 1), kept(2, t - 1), kept(3, t - 1), 4)
                           : step(state(t - 1), state(t), yA, yB, yA, 4);
                 if (st != FH_OK) return st;
             }
-            if (keep) {
+            if (keep && !have) {
                 st = step(state(len - 1), nullptr, kept(1, len - 1), kept(2, len - 1), kept(3, len - 1), 3);
                 if (st != FH_OK) return st;
             }

@@ -49,7 +49,7 @@ struct fh_basis {
     int num_cu = 0;
     int grid_cap = 0;              // max persistent workgroups
     int blocks_per_cu = 0;         // 0 = occupancy limit
-    int xcd_order = 1;
+    int xcd_order = 2;             // fh_basis_set_launch; 2 = one contiguous eighth of the tiles per XCD
     int tile_order = 0;            // fh_basis_set_tile_order
     int prefix_modes = 0;
     const fh::KernelSet* ks = nullptr;

@@ -261,17 +261,25 @@ def test_batched_equals_per_sector_bitwise():
 @pytest.mark.parametrize("blocks_per_cu,xcd_order", [(0, 1), (1, 0), (2, 1), (0, 2), (3, 2)])
 def test_schedule_does_not_change_results(blocks_per_cu, xcd_order):
     """Tile order, persistent grid size and XCD mapping only change which
-    workgroup computes a row, never the row's arithmetic."""
+    workgroup computes a row, never the row's arithmetic (one and four
+    columns; a fused RK4 step too)."""
     M = 6
     sectors = W.all_sectors(M, 16)
     model = fh.Model(M, W.omega_quadratic(M), 0.05, W.V_longrange(M))
     b = fh.Basis(M, sectors)
     x = torch.from_numpy(W.random_psi(b.total, 3)).cuda()
-    ref = fh.apply_h(model, b, x)
+    x4 = torch.from_numpy(W.random_psi(b.total, 4, 4)).cuda()
+    ref, ref4 = fh.apply_h(model, b, x), fh.apply_h(model, b, x4)
+    y = x.clone()
+    fh.evolve_rk4(model, b, y, 1e-3, 2)
     b.set_launch(blocks_per_cu, xcd_order)
     for order, prefix in ((1, 3), (0, 0), (1, 2), (0, 4), (1, 5)):
         b.set_tile_order(order, prefix)
         assert torch.equal(fh.apply_h(model, b, x), ref)
+        assert torch.equal(fh.apply_h(model, b, x4), ref4)
+    z = x.clone()
+    fh.evolve_rk4(model, b, z, 1e-3, 2)
+    assert torch.equal(z, y)
 
 
 def test_rk4_fieldnumber_multi_rhs():
@@ -331,6 +339,10 @@ def test_adjoint_vs_oracle():
         res2 = fh.adjoint_rk4(model, b, psi0, dt, nsteps, 7, obj, mode=1, keep_stage_inputs=False)
         assert np.array_equal(res["lambda0"].cpu().numpy(), res2["lambda0"].cpu().numpy())
         assert res["dLambda"][0] == res2["dLambda"][0] and np.array_equal(res["dV"], res2["dV"])
+        # one segment (every state and stage input kept from the forward sweep) changes no bit
+        res3 = fh.adjoint_rk4(model, b, psi0, dt, nsteps, nsteps, obj, mode=1)
+        assert np.array_equal(res["lambda0"].cpu().numpy(), res3["lambda0"].cpu().numpy())
+        assert res["dLambda"][0] == res3["dLambda"][0] and np.array_equal(res["dV"], res3["dV"])
         assert abs(res["J"][0] - ref["J"]) <= 1e-10
         assert abs(res["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
         # only momentum-conserving entries are parameters of the model; the

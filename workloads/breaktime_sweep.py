@@ -43,6 +43,44 @@ def poisson_nmax(mean: float, weight: float = 0.999) -> int:
     return N
 
 
+def squeezing_onset_prediction(V, Lam, z):
+    """Sec. II.E: the single-field estimate of the squeezing onset,
+    t_sqz = 0.05 n_tot / |<H_int>|, with the classical interaction energy
+    <H_int> = (Lambda/2) sum V_ijkl z_i* z_j* z_k z_l of the initial field z.
+    Returns (t_sqz, n_tot, <H_int>); t_sqz is inf without interaction energy."""
+    z = np.asarray(z, dtype=np.complex128)
+    n_tot = float(np.sum(np.abs(z) ** 2))
+    e_int = 0.5 * Lam * np.einsum("ijkl,i,j,k,l->", V, z.conj(), z.conj(), z, z)
+    t_pred = 0.05 * n_tot / abs(e_int) if e_int != 0 else float("inf")
+    return t_pred, n_tot, e_int
+
+
+def refine_minimum(t, v):
+    """Deepest sample of v(t) refined by the parabola through it and its two
+    neighbours (when both exist, are finite and the parabola opens upward).
+    Returns (t_min, v_min), or (nan, nan) if no sample is finite."""
+    v = np.asarray(v, dtype=np.float64)
+    t = np.asarray(t, dtype=np.float64)
+    if not np.isfinite(v).any():
+        return float("nan"), float("nan")
+    k = int(np.nanargmin(v))
+    t_min, v_min = float(t[k]), float(v[k])
+    if 0 < k < len(v) - 1 and np.all(np.isfinite(v[k - 1:k + 2])):
+        y0, y1, y2 = v[k - 1], v[k], v[k + 1]
+        den = y0 - 2.0 * y1 + y2
+        if den > 0:
+            off = 0.5 * (y0 - y2) / den
+            t_min = float(t[k] + off * (t[k + 1] - t[k]))
+            v_min = float(y1 - 0.25 * (y0 - y2) * off)
+    return t_min, v_min
+
+
+def classical_distance(n_modes, n_classical, n_tot):
+    """Sec. IV.B comparison: sum_k |<n_k>(t) - |alpha_k(t)|^2| / n_tot per record
+    (rows of n_modes and n_classical are records, columns modes)."""
+    return np.abs(np.asarray(n_modes) - np.asarray(n_classical)).sum(axis=1) / n_tot
+
+
 def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float, classical: bool = False,
         t_ref: float = 1.0):
     import torch
@@ -65,9 +103,7 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
         psi, zc = fh.init_coherent(b, w.init_params[0]), w.init_params[0]
     else:
         psi, zc = fh.init_fieldnumber(b, w.init_params[0]), w.init_params[0]
-    n_tot = float(np.sum(np.abs(zc) ** 2))
-    e_int = 0.5 * w.Lambda * np.einsum("ijkl,i,j,k,l->", w.V, zc.conj(), zc.conj(), zc, zc)
-    t_pred = 0.05 * n_tot / abs(e_int) if e_int != 0 else float("inf")
+    t_pred, n_tot, e_int = squeezing_onset_prediction(w.V, w.Lambda, zc)
     rho = margin * fh.spectral_radius(model, b) + 1e-9
     work = torch.empty((4 * b.total,), dtype=torch.complex128, device="cuda")
     t0 = time.time()
@@ -95,18 +131,8 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
            "h_applies": int(round(t_now / interval)) * terms_per_step, "wall_s": time.time() - t0}
     # deepest squeezing within the run (Sec. IV.E): V_min and tau_min = n_tot |chi| t_min,
     # the minimum refined by the parabola through the three samples around it
-    vm = np.array(series["vminus"], dtype=np.float64)
-    tt = np.array(series["t"], dtype=np.float64)
-    if np.isfinite(vm).any():
-        k = int(np.nanargmin(vm))
-        t_min, v_min = float(tt[k]), float(vm[k])
-        if 0 < k < len(vm) - 1 and np.all(np.isfinite(vm[k - 1:k + 2])):
-            y0, y1, y2 = vm[k - 1], vm[k], vm[k + 1]
-            den = y0 - 2.0 * y1 + y2
-            if den > 0:
-                off = 0.5 * (y0 - y2) / den
-                t_min = float(tt[k] + off * (tt[k + 1] - tt[k]))
-                v_min = float(y1 - 0.25 * (y0 - y2) * off)
+    t_min, v_min = refine_minimum(series["t"], series["vminus"])
+    if np.isfinite(v_min):
         n_chi = abs(e_int) / n_tot
         out.update(vminus_min=v_min, t_vminus_min=t_min, tau_min=n_chi * t_min, n_chi=n_chi)
     if classical:
@@ -114,7 +140,7 @@ def run(problem: str, r: int, interval: float, t_max: float, seed, margin: float
         nrec = len(series["t"])
         _, traj = fh.classical_rk4(model, zc, interval / sub, (nrec - 1) * sub, every=sub)
         ncl = (traj[:, 0, :].abs() ** 2).cpu().numpy()
-        dev = np.abs(np.array(series["n_modes"]) - ncl).sum(axis=1) / n_tot
+        dev = classical_distance(series["n_modes"], ncl, n_tot)
         tt = np.array(series["t"])
         out["classical"] = {"t_ref": t_ref, "dev_at_t_ref": float(np.interp(t_ref, tt, dev)),
                             "dev_max": float(dev.max()), "dev_at_0": float(dev[0])}
