@@ -96,19 +96,23 @@ def _oracle_rows_worker(job):
 
 
 def adjoint_checkpoints(torch, nsteps: int, vec_bytes: int, frac: float = 0.8):
-    """Checkpoint interval for fh_adjoint_rk4 that uses the free device memory:
-    the largest C <= nsteps whose work buffer with kept stage inputs (segments +
-    4C + 10 state vectors) fits in frac of what is free; else the largest C
-    with recomputed stage inputs (segments + C + 10).  Returns (C, kept)."""
+    """Checkpoint interval for fh_adjoint_rk4 that uses the free device memory.
+    With kept stage inputs the last segment is kept from the forward sweep and
+    every other segment is recomputed once, so the recompute is (segments - 1)
+    x C steps: take the fewest segments, each of C = ceil(nsteps / segments)
+    steps, whose work buffer (segments + 4C + 10 state vectors) fits in frac of
+    what is free; else the largest C with recomputed stage inputs (segments +
+    C + 10).  Returns (C, kept)."""
     torch.cuda.empty_cache()  # blocks cached by torch count as free here
     free, _ = torch.cuda.mem_get_info()
     budget = frac * free
-    for kept in (True, False):
-        for C in range(nsteps, 0, -1):
-            nseg = -(-nsteps // C)
-            vecs = nseg + (4 * C if kept else C) + 10
-            if vecs * vec_bytes <= budget:
-                return C, kept
+    for nseg in range(1, nsteps + 1):
+        C = -(-nsteps // nseg)
+        if (-(-nsteps // C) + 4 * C + 10) * vec_bytes <= budget:
+            return C, True
+    for C in range(nsteps, 0, -1):
+        if (-(-nsteps // C) + C + 10) * vec_bytes <= budget:
+            return C, False
     return 1, False
 
 
@@ -160,6 +164,37 @@ def copy_bandwidth(torch, nbytes=1 << 31, runs=10):
     del a, b
     torch.cuda.empty_cache()
     return 2.0 * nbytes / ts[len(ts) // 2] / 1e9
+
+
+def apply_only(fh, torch, which: str, launches: int) -> dict:
+    """H psi (APPLY) launches alone on one workload, for profiling: the one
+    large sector (one column), or the field-number draws (M = 10, N = 30, all
+    10 P) with one column (draw 0) or all 16 draws as one vector.  Default
+    launch schedule of the basis.  Returns per-launch milliseconds (HIP events
+    on the launch stream) after one warm-up launch."""
+    import workloads as W
+
+    w = W.large_sector() if which == "one_large_sector" else W.fieldnumber_draws(16, 30)
+    model, basis = fh.Model(w.M, w.omega, w.Lambda, w.V), fh.Basis(w.M, w.sectors)
+    if w.init == "number":
+        x, nrhs = fh.init_number(basis, w.init_params), 1
+    else:
+        nrhs = 16 if which == "fieldnumber_16" else 1
+        x = fh.init_fieldnumber(basis, w.init_params if nrhs > 1 else w.init_params[0])
+    print(f"[bench] apply-only {which}: {basis.total} states x {nrhs}", file=sys.stderr, flush=True)
+    out = torch.empty_like(x)
+    fh.apply_h(model, basis, x, out)
+    ms = []
+    for _ in range(launches):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fh.apply_h(model, basis, x, out)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = sorted(ms)[len(ms) // 2]
+    return {"apply_only": which, "states": basis.total, "rhs": nrhs, "launch_ms": ms, "median_ms": med,
+            "ns_per_row_column": med * 1e6 / (basis.total * nrhs)}
 
 
 def host_info() -> dict:
@@ -480,6 +515,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the batched / multi-rhs / adjoint comparisons")
     ap.add_argument("--forms-only", action="store_true", help="run only the form comparisons (one JSON object)")
+    ap.add_argument("--apply-only", choices=["one_large_sector", "fieldnumber_1", "fieldnumber_16"], default=None,
+                    help="only time --launches H psi launches (APPLY) on this workload (for profilers)")
+    ap.add_argument("--launches", type=int, default=3)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the launch schedule given by the next four options instead of the autotuner's")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -506,6 +544,9 @@ def main():
     import paper_2111_00050_amd as fh
 
     torch.cuda.set_device(0)
+    if args.apply_only:
+        print(json.dumps(apply_only(fh, torch, args.apply_only, args.launches)), flush=True)
+        return
     if args.forms_only:
         print(json.dumps({"forms": forms()}), flush=True)
         return

@@ -840,7 +840,7 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
 // uniform over the workgroup and each class body holds its own sums, so the
 // registers are those of the largest class, not of all of them.
 template <int M>
-__global__ __launch_bounds__(kTileRows) void corr_kernel(CorrArgs A) {
+__global__ __launch_bounds__(kTileRows, 2) void corr_kernel(CorrArgs A) {
     static_for<0, M>([&](auto Cc) {
         constexpr int c = decltype(Cc)::value;
         if ((int)blockIdx.y == c) {
