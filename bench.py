@@ -46,19 +46,6 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def profiled_launch(states: int):
-    """Launch schedule recorded with the committed counters, if they were taken
-    on the current kernel source and this sector."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_sha") != kernel_hash() or t.get("states") != states or "launch" not in t:
-        return None
-    return dict(t["launch"])
-
-
 def measured_traffic(states: int, launch: dict):
     """HBM bytes per stage launch from committed rocprofv3 PMC counters, if
     they were taken on the current kernel source with the same launch
@@ -518,10 +505,11 @@ def main():
     ap.add_argument("--apply-only", choices=["one_large_sector", "fieldnumber_1", "fieldnumber_16"], default=None,
                     help="only time --launches H psi launches (APPLY) on this workload (for profilers)")
     ap.add_argument("--launches", type=int, default=3)
-    ap.add_argument("--no-autotune", action="store_true",
-                    help="use the launch schedule given by the next four options instead of the autotuner's")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let fh_basis_autotune pick the launch schedule instead of the next four options")
+    ap.add_argument("--no-autotune", action="store_true", help="(the default) use the next four options")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--xcd-order", type=int, default=1)
+    ap.add_argument("--xcd-order", type=int, default=3)
     ap.add_argument("--tile-order", type=int, default=0)
     ap.add_argument("--prefix-modes", type=int, default=0)
     args = ap.parse_args()
@@ -555,18 +543,13 @@ def main():
     basis = fh.Basis(w.M, w.sectors)
     D = basis.total
     psi = fh.init_number(basis, w.init_params)
-    if args.no_autotune:
+    if not args.autotune:
+        # the given schedule (default: every workgroup the CU holds, the per-XCD
+        # tile queue over contiguous eighths, plain 256-row tiles)
         basis.set_launch(args.blocks_per_cu, args.xcd_order)
         basis.set_tile_order(args.tile_order, args.prefix_modes)
         launch = {"blocks_per_cu": args.blocks_per_cu, "xcd_order": args.xcd_order,
                   "tile_order": args.tile_order, "prefix_modes": args.prefix_modes, "autotuned": False}
-    elif profiled_launch(D) is not None:
-        # the schedule the autotuner chose when the committed counters were
-        # taken on this kernel source (so that 'traffic' applies to this run)
-        launch = profiled_launch(D)
-        basis.set_launch(launch["blocks_per_cu"], launch["xcd_order"])
-        basis.set_tile_order(launch["tile_order"], launch["prefix_modes"])
-        launch["autotuned"] = "when profiled"
     else:
         # untimed: pick the launch schedule of the stage kernel for this basis
         launch, _ = fh.autotune(model, basis, psi)

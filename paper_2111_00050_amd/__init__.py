@@ -189,7 +189,7 @@ class Basis:
 
     __del__ = close
 
-    def set_launch(self, blocks_per_cu=0, xcd_order=2):
+    def set_launch(self, blocks_per_cu=0, xcd_order=3):
         _check(_lib.fh_basis_set_launch(self._h, int(blocks_per_cu), int(xcd_order)))
 
     def set_tile_order(self, order=1, prefix_modes=3):

@@ -236,6 +236,7 @@ void basis_free(fh_basis* b) {
     (void)hipFree(b->d_secs);
     (void)hipFree(b->d_tiles);
     (void)hipFree(b->d_secmap);
+    (void)hipFree(b->d_queue);
     (void)hipFree(b->d_partial);
     (void)hipFree(b->d_small);
     (void)hipFree(b->d_occ);
@@ -329,6 +330,7 @@ fh_status make_basis(int M, int pmod, int nsec, const int32_t* N, const int32_t*
     if ((e = hipMalloc(&b->d_tiles, sizeof(Tile) * ntile)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_secmap, sizeof(int) * b->secmap.size())) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_partial, sizeof(double) * b->partial_doubles)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->d_queue, 64)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_small, sizeof(double) * b->small_doubles)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMemcpy(b->d_T, b->T.data(), sizeof(int) * b->T.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "hipMemcpy");
@@ -425,6 +427,7 @@ StageArgs stage_base(const fh_model* m, const fh_basis* b) {
     a.nsqrt = (int)b->sqrt_tab.size();
     a.secs = b->d_secs;
     a.xcd_order = b->xcd_order;
+    a.queue = b->d_queue;
     return a;
 }
 
@@ -506,6 +509,7 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
             if (nt == 0) continue;
             a.tiles = b->d_tiles + b->tile_begin[sec];
             a.ntiles = nt;
+            a.queue = nullptr;  // per-sector launches walk their tiles as in order 2
             b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
         }
     } else {
@@ -513,6 +517,11 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
         if (nt > 0) {
             a.tiles = b->d_tiles;
             a.ntiles = nt;
+            if (a.xcd_order == 3) {
+                // the eight XCD counters start at zero (a fill kernel: also valid under graph capture)
+                launch_fill(reinterpret_cast<double*>(b->d_queue), 4, 0.0, s);
+                FH_HIP(hipGetLastError());
+            }
             b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
         }
     }
@@ -700,7 +709,7 @@ fh_status fh_basis_sizes(const fh_basis* b, int64_t* dim, int64_t* offset) {
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order) {
     FH_REQUIRE(b != nullptr, FH_EINVAL, "fh_basis_set_launch: basis is NULL");
     FH_REQUIRE(blocks_per_cu >= 0 && blocks_per_cu <= 8, FH_EINVAL, "blocks_per_cu must be in [0, 8]");
-    FH_REQUIRE(xcd_order >= 0 && xcd_order <= 2, FH_EINVAL, "xcd_order must be 0, 1 or 2");
+    FH_REQUIRE(xcd_order >= 0 && xcd_order <= 3, FH_EINVAL, "xcd_order must be 0, 1, 2 or 3");
     b->blocks_per_cu = blocks_per_cu;
     b->xcd_order = xcd_order;
     return FH_OK;
@@ -1005,7 +1014,7 @@ fh_status fh_basis_autotune(const fh_model* m, fh_basis* b, int nrhs, const fh_c
             std::vector<std::array<int, 4>> cands;
             const int maxp = std::min(b->M - 1, 3);
             for (int bpc : {0, 1, 2, 3})
-                for (int xo : {2, 1, 0})
+                for (int xo : {3, 2, 1, 0})
                     for (int pre = 0; pre <= maxp; ++pre) {
                         if (pre == 1) continue;  // a one-mode prefix never pays
                         cands.push_back({bpc, xo, pre > 0 ? 1 : 0, pre});

@@ -145,6 +145,7 @@ struct StageArgs {
     int ntiles;
     const SecInfo* secs;
     int xcd_order;
+    unsigned* queue;      // xcd_order 3: one tile counter per XCD, zero at launch
 };
 
 // Moments / one-body kernels.

@@ -56,12 +56,16 @@ __device__ __forceinline__ int virtual_block(int xcd_order) {
 //   xcd_order 1: the XCDs take contiguous chunks of G/8 units in turn
 //   xcd_order 2: XCD x walks the x-th contiguous eighth of all units, so its
 //                L2 sees one sliding neighbourhood of the state vector
+//   xcd_order 3: the stage kernel takes the units of XCD x's eighth in order
+//                from a counter of that XCD (next_unit), so that the units in
+//                flight on an XCD stay one compact run however the workgroups
+//                drift; other kernels walk as in order 2
 struct UnitWalk {
     int first, end, step;
 };
 __device__ __forceinline__ UnitWalk unit_walk(int xcd_order, int nunits) {
     const int b = blockIdx.x, G = gridDim.x;
-    if (xcd_order == 2 && (G & 7) == 0) {
+    if ((xcd_order == 2 || xcd_order == 3) && (G & 7) == 0) {
         const int x = b & 7;
         const int lo = (int)((long long)nunits * x / 8), hi = (int)((long long)nunits * (x + 1) / 8);
         return UnitWalk{lo + (b >> 3), hi, G >> 3};
@@ -259,7 +263,24 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
     const __attribute__((address_space(4))) SecInfo* secs =
         (const __attribute__((address_space(4))) SecInfo*)A.secs;
     const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles * G);
-    for (int vt = walk.first; vt < walk.end; vt += walk.step) {
+    // Order 3: the next unit of this XCD's eighth comes from its counter (one
+    // vector atomic per workgroup and unit); every workgroup leaves once the
+    // counter has passed the end of the eighth.
+    const bool queued = A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
+    __shared__ int s_unit;
+    for (int vt = walk.first;; vt += walk.step) {
+        if (queued) {
+            __syncthreads();  // every thread has read the previous unit
+            if (threadIdx.x == 0) {
+                const int lo = walk.first - (int)(blockIdx.x >> 3);  // start of this XCD's eighth
+                const unsigned k = __hip_atomic_fetch_add(A.queue + (blockIdx.x & 7), 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                s_unit = k < (unsigned)(walk.end - lo) ? lo + (int)k : walk.end;
+            }
+            __syncthreads();
+            vt = __builtin_amdgcn_readfirstlane(s_unit);
+        }
+        if (vt >= walk.end) break;
         const int tsec = __builtin_amdgcn_readfirstlane(tiles[vt / G].sec);
         const int row0 = __builtin_amdgcn_readfirstlane(tiles[vt / G].row0);
         const int nrows = __builtin_amdgcn_readfirstlane(tiles[vt / G].nrows);

@@ -40,6 +40,7 @@ struct fh_basis {
     fh::SecInfo* d_secs = nullptr;
     fh::Tile* d_tiles = nullptr;
     int* d_secmap = nullptr;
+    unsigned* d_queue = nullptr;   // xcd_order 3: per-XCD tile counters of the stage kernel
     double* d_partial = nullptr;   // reduction partials
     size_t partial_doubles = 0;
     double* d_small = nullptr;     // reduced values, coefficient tables, ...
@@ -49,7 +50,7 @@ struct fh_basis {
     int num_cu = 0;
     int grid_cap = 0;              // max persistent workgroups
     int blocks_per_cu = 0;         // 0 = occupancy limit
-    int xcd_order = 2;             // fh_basis_set_launch; 2 = one contiguous eighth of the tiles per XCD
+    int xcd_order = 3;             // fh_basis_set_launch; 3 = per-XCD tile queue over contiguous eighths
     int tile_order = 0;            // fh_basis_set_tile_order
     int prefix_modes = 0;
     const fh::KernelSet* ks = nullptr;
