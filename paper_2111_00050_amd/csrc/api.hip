@@ -330,7 +330,7 @@ fh_status make_basis(int M, int pmod, int nsec, const int32_t* N, const int32_t*
     if ((e = hipMalloc(&b->d_tiles, sizeof(Tile) * ntile)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_secmap, sizeof(int) * b->secmap.size())) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_partial, sizeof(double) * b->partial_doubles)) != hipSuccess) return fail(e, "hipMalloc");
-    if ((e = hipMalloc(&b->d_queue, 64)) != hipSuccess) return fail(e, "hipMalloc");
+    if ((e = hipMalloc(&b->d_queue, kQueueBytes)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMalloc(&b->d_small, sizeof(double) * b->small_doubles)) != hipSuccess) return fail(e, "hipMalloc");
     if ((e = hipMemcpy(b->d_T, b->T.data(), sizeof(int) * b->T.size(), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e, "hipMemcpy");
@@ -1294,6 +1294,7 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
     a.partial = b->d_partial;
     a.xcd_order = b->xcd_order;
     a.occ = b->d_occ;
+    a.queue = b->d_queue;
     const int G = persistent_grid(b, b->ks->corr_fn, lds, nt);
     const int per = corr_pairs_per_launch(M);
     for (int p0 = 0; p0 < kCorrPairs; p0 += per) {
@@ -1301,6 +1302,10 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
             a.u[q] = u[p0 + q];
             a.y[q] = y[p0 + q];
             a.uscale[q] = uscale[p0 + q];
+        }
+        if (a.xcd_order == 3) {
+            launch_fill(reinterpret_cast<double*>(b->d_queue), 4 * M, 0.0, s);  // counters [class][XCD] = 0
+            FH_HIP(hipGetLastError());
         }
         b->ks->corr(a, G, M, lds, s);  // one row of workgroups per momentum class
         FH_HIP(hipGetLastError());

@@ -222,6 +222,7 @@ struct CorrArgs {
     const SecInfo* secs;
     double* partial;    // [class][grid][kCorrOutMax] complex
     int xcd_order;
+    unsigned* queue;    // xcd_order 3: tile counters [class][XCD], zero at launch
 };
 constexpr int kCorrOutMax = 36;  // (max class size)^2 for M <= 10
 

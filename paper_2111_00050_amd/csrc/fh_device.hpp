@@ -724,7 +724,27 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     const __attribute__((address_space(4))) SecInfo* secs =
         (const __attribute__((address_space(4))) SecInfo*)A.secs;
     const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles);
-    for (int t = walk.first; t < walk.end; t += walk.step) {
+    // Order 3: this class's workgroups on an XCD take its tiles in order from
+    // the counter of (class, XCD), as in the stage kernel.  Not at M >= 8, where
+    // the class's sums fill the registers and the queue's barriers made the
+    // compiler spill (108 B per lane at M = 8, 440 B at M = 10); there the walk
+    // is order 2.
+    constexpr bool kQueue = M <= 7;
+    const bool queued = kQueue && A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
+    __shared__ int s_unit;
+    for (int t = walk.first;; t += walk.step) {
+        if (queued) {
+            __syncthreads();  // every thread has read the previous tile
+            if (threadIdx.x == 0) {
+                const int lo = walk.first - (int)(blockIdx.x >> 3);
+                const unsigned k = __hip_atomic_fetch_add(A.queue + 8 * C + (blockIdx.x & 7), 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+                s_unit = k < (unsigned)(walk.end - lo) ? lo + (int)k : walk.end;
+            }
+            __syncthreads();
+            t = __builtin_amdgcn_readfirstlane(s_unit);
+        }
+        if (t >= walk.end) break;
         const int tsec = __builtin_amdgcn_readfirstlane(tiles[t].sec);
         const int row0 = __builtin_amdgcn_readfirstlane(tiles[t].row0);
         const int nrows = __builtin_amdgcn_readfirstlane(tiles[t].nrows);

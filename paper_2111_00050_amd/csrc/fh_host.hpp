@@ -40,7 +40,7 @@ struct fh_basis {
     fh::SecInfo* d_secs = nullptr;
     fh::Tile* d_tiles = nullptr;
     int* d_secmap = nullptr;
-    unsigned* d_queue = nullptr;   // xcd_order 3: per-XCD tile counters of the stage kernel
+    unsigned* d_queue = nullptr;   // xcd_order 3: tile counters ([class][XCD] for the correlators)
     double* d_partial = nullptr;   // reduction partials
     size_t partial_doubles = 0;
     double* d_small = nullptr;     // reduced values, coefficient tables, ...
@@ -62,6 +62,7 @@ struct fh_basis {
 };
 
 namespace fh {
+constexpr size_t kQueueBytes = 8 * kMaxM * sizeof(unsigned);  // tile counters of XCD order 3
 void set_error(const std::string& msg);
 fh_status hip_fail(hipError_t e, const char* what);
 size_t lds_bytes(const fh_basis* b, int extra_doubles);
