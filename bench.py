@@ -544,8 +544,8 @@ def main():
     D = basis.total
     psi = fh.init_number(basis, w.init_params)
     if not args.autotune:
-        # the given schedule (default: every workgroup the CU holds, the per-XCD
-        # tile queue over contiguous eighths, plain 256-row tiles)
+        # the given schedule (default: every workgroup the CU holds, per-XCD
+        # tile queues over chunks dealt to the XCDs in turn, plain 256-row tiles)
         basis.set_launch(args.blocks_per_cu, args.xcd_order)
         basis.set_tile_order(args.tile_order, args.prefix_modes)
         launch = {"blocks_per_cu": args.blocks_per_cu, "xcd_order": args.xcd_order,

@@ -243,10 +243,11 @@ fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c
  * workgroups per compute unit (0 = occupancy limit) and the XCD-aware tile
  * order (0 = plain round robin, 1 = the XCDs take contiguous chunks of tiles
  * in turn, 2 = each XCD walks one contiguous eighth of the tile list, 3 = the
- * same eighths, but the workgroups of an XCD take its tiles in order from a
- * counter of that XCD, so that the tiles in flight stay one compact run; the
- * counters live in the basis, so with order 3 stage launches on one basis
- * must not overlap on different streams).  A new basis starts at (0, 3).
+ * chunks of order 1, each XCD taking the tiles of its chunks in order from a
+ * counter of that XCD, so that the tiles in flight on an XCD stay one compact
+ * run; with order 3 the counters live in the basis, so stage and adjoint
+ * launches on one basis must not overlap on different streams).  A new basis
+ * starts at (0, 3).
  * Not thread-safe with concurrent calls on the same basis. */
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
 /* Tiling and schedule of each sector's rows; storage stays lexicographic and

@@ -40,6 +40,14 @@ constexpr FH_HD int stage_lanes_per_row(int nrhs) { return nrhs >= 4 ? 4 : nrhs;
 // Occupancy target of the stage kernel (workgroups of 256 per CU); it caps the
 // registers per thread at 512 / (4 * blocks) per SIMD lane.
 constexpr int kStageBlocksPerCU = FH_STAGE_BLOCKS_PER_CU;
+// Minimum workgroups per CU the one-column stage kernel is compiled for: the
+// occupancy its register count reaches without the tile-queue loop (M <= 6:
+// <= 128 VGPRs, 4 waves per SIMD; M = 7, 8: <= 168, 3; M >= 9: 2), so that the
+// queue's few extra registers do not cost a wave per SIMD.  Several columns:
+// no bound (the 16-column kernel holds 256 VGPRs at one wave).
+constexpr FH_HD int stage_min_blocks(int M, int nrhs) {
+    return nrhs > 1 ? kStageBlocksPerCU : (M <= 6 ? 4 : M <= 8 ? 3 : 2);
+}
 
 template <int M>
 struct PairTable {
@@ -145,7 +153,7 @@ struct StageArgs {
     int ntiles;
     const SecInfo* secs;
     int xcd_order;
-    unsigned* queue;      // xcd_order 3: one tile counter per XCD, zero at launch
+    unsigned* queue;      // xcd_order 3, 4: one tile counter per XCD, zero at launch
 };
 
 // Moments / one-body kernels.

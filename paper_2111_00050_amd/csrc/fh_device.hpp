@@ -56,21 +56,35 @@ __device__ __forceinline__ int virtual_block(int xcd_order) {
 //   xcd_order 1: the XCDs take contiguous chunks of G/8 units in turn
 //   xcd_order 2: XCD x walks the x-th contiguous eighth of all units, so its
 //                L2 sees one sliding neighbourhood of the state vector
-//   xcd_order 3: the stage kernel takes the units of XCD x's eighth in order
-//                from a counter of that XCD (next_unit), so that the units in
-//                flight on an XCD stay one compact run however the workgroups
-//                drift; other kernels walk as in order 2
+//   xcd_order 3: chunks of about G/8 units dealt to the XCDs round robin (as
+//                in order 1), each XCD taking its chunks' units in order from a
+//                counter of that XCD (queued_unit): the units in flight on an
+//                XCD stay one compact run however its workgroups drift, and all
+//                XCDs work in one window of the vector, which the memory-side
+//                cache shares.  Kernels without counters walk it as order 1.
 struct UnitWalk {
     int first, end, step;
 };
 __device__ __forceinline__ UnitWalk unit_walk(int xcd_order, int nunits) {
     const int b = blockIdx.x, G = gridDim.x;
-    if ((xcd_order == 2 || xcd_order == 3) && (G & 7) == 0) {
+    if (xcd_order == 2 && (G & 7) == 0) {
         const int x = b & 7;
         const int lo = (int)((long long)nunits * x / 8), hi = (int)((long long)nunits * (x + 1) / 8);
         return UnitWalk{lo + (b >> 3), hi, G >> 3};
     }
     return UnitWalk{virtual_block(xcd_order == 0 ? 0 : 1), nunits, G};
+}
+
+// Order 3: the unit of this XCD's k-th ticket (k from its counter, the same
+// for the whole workgroup), or nunits when the XCD has none left.  Chunks of K
+// units, K the power of two >= G/8 (about one unit per workgroup of the XCD),
+// so that the arithmetic is shifts.  Grid a multiple of 8.
+__device__ __forceinline__ int queued_unit(int nunits, unsigned k) {
+    const unsigned per = gridDim.x >> 3;
+    const unsigned L = per <= 1 ? 0u : 32u - (unsigned)__builtin_clz(per - 1u);
+    const unsigned long long u = ((((unsigned long long)(k >> L)) * 8u + (blockIdx.x & 7u)) << L) |
+                                 (k & ((1u << L) - 1u));
+    return u < (unsigned long long)nunits ? (int)u : nunits;
 }
 
 template <int M>
@@ -230,7 +244,7 @@ __device__ __forceinline__ void load_occ(const unsigned char* occ, long long sta
 
 // ------------------------------------------------------------ H psi stage --
 template <int M, int NRHS>
-__global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(StageArgs A) {
+__global__ __launch_bounds__(kTileRows, stage_min_blocks(M, NRHS)) void stage_kernel(StageArgs A) {
     using CB = Combos<M>;
     constexpr int NP = CB::NP;
     extern __shared__ int smem[];
@@ -266,17 +280,17 @@ __global__ __launch_bounds__(kTileRows, kStageBlocksPerCU) void stage_kernel(Sta
     // Order 3: the next unit of this XCD's eighth comes from its counter (one
     // vector atomic per workgroup and unit); every workgroup leaves once the
     // counter has passed the end of the eighth.
+    // Order 3: the next unit comes from this XCD's counter (one vector atomic
+    // per workgroup and unit); every workgroup leaves once its XCD has no unit
+    // left.
     const bool queued = A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
     __shared__ int s_unit;
     for (int vt = walk.first;; vt += walk.step) {
         if (queued) {
             __syncthreads();  // every thread has read the previous unit
-            if (threadIdx.x == 0) {
-                const int lo = walk.first - (int)(blockIdx.x >> 3);  // start of this XCD's eighth
-                const unsigned k = __hip_atomic_fetch_add(A.queue + (blockIdx.x & 7), 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                s_unit = k < (unsigned)(walk.end - lo) ? lo + (int)k : walk.end;
-            }
+            if (threadIdx.x == 0)
+                s_unit = queued_unit(walk.end, __hip_atomic_fetch_add(A.queue + (blockIdx.x & 7), 1u,
+                                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             __syncthreads();
             vt = __builtin_amdgcn_readfirstlane(s_unit);
         }
@@ -731,18 +745,15 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     // is order 2.
     constexpr bool kQueue = M <= 7;
     const bool queued = kQueue && A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
-    __shared__ int s_unit;
+    __shared__ unsigned s_ticket;
     for (int t = walk.first;; t += walk.step) {
         if (queued) {
-            __syncthreads();  // every thread has read the previous tile
-            if (threadIdx.x == 0) {
-                const int lo = walk.first - (int)(blockIdx.x >> 3);
-                const unsigned k = __hip_atomic_fetch_add(A.queue + 8 * C + (blockIdx.x & 7), 1u, __ATOMIC_RELAXED,
-                                                          __HIP_MEMORY_SCOPE_AGENT);
-                s_unit = k < (unsigned)(walk.end - lo) ? lo + (int)k : walk.end;
-            }
+            __syncthreads();  // every thread has read the previous ticket
+            if (threadIdx.x == 0)
+                s_ticket = __hip_atomic_fetch_add(A.queue + 8 * C + (blockIdx.x & 7), 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
             __syncthreads();
-            t = __builtin_amdgcn_readfirstlane(s_unit);
+            t = queued_unit(walk.end, __builtin_amdgcn_readfirstlane(s_ticket));
         }
         if (t >= walk.end) break;
         const int tsec = __builtin_amdgcn_readfirstlane(tiles[t].sec);

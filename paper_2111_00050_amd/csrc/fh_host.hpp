@@ -50,7 +50,7 @@ struct fh_basis {
     int num_cu = 0;
     int grid_cap = 0;              // max persistent workgroups
     int blocks_per_cu = 0;         // 0 = occupancy limit
-    int xcd_order = 3;             // fh_basis_set_launch; 3 = per-XCD tile queue over contiguous eighths
+    int xcd_order = 3;             // fh_basis_set_launch; 3 = per-XCD tile queues over interleaved chunks
     int tile_order = 0;            // fh_basis_set_tile_order
     int prefix_modes = 0;
     const fh::KernelSet* ks = nullptr;

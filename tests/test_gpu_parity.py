@@ -258,7 +258,8 @@ def test_batched_equals_per_sector_bitwise():
     assert torch.equal(p1, p2)
 
 
-@pytest.mark.parametrize("blocks_per_cu,xcd_order", [(0, 1), (1, 0), (2, 1), (0, 2), (3, 2), (0, 3), (2, 3)])
+@pytest.mark.parametrize("blocks_per_cu,xcd_order",
+                         [(0, 1), (1, 0), (2, 1), (0, 2), (3, 2), (0, 3), (1, 3), (2, 3)])
 def test_schedule_does_not_change_results(blocks_per_cu, xcd_order):
     """Tile order, persistent grid size and XCD mapping only change which
     workgroup computes a row, never the row's arithmetic (one and four
