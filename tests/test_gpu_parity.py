@@ -1010,3 +1010,20 @@ def test_squeezing_of_a_site_kerr_state_on_gpu():
         m2 = beta[x] ** 2 * np.exp(-1j * Lam * M * t) * np.exp(n * (np.exp(-2j * Lam * M * t) - 1))
         want = 1.0 + 2.0 * (n - abs(m1) ** 2) - 2.0 * abs(m2 - m1 * m1)
         assert abs(g["vminus"] - want) <= 1e-8, (t, g["vminus"], want)
+
+
+def test_tangent_at_tiny_interaction():
+    """At a tiny nonzero Lambda the tangent takes G y by its own application
+    (deriving it from H y would cost eps |omega.n| / |Lambda G| of accuracy):
+    dJ/dLambda at Lambda = 1e-8 against the oracle's adjoint and the GPU
+    adjoint."""
+    M, dt, nsteps, Lam = 4, 5e-3, 20, 1e-8
+    sectors = W.all_sectors(M, 8)
+    omega, V = W.omega_quadratic(M), W.V_longrange(M)
+    orc, model, b = _pair(M, sectors, omega, Lam, V)
+    alpha = W.coherent_amplitudes(33, M, 1.4)
+    ref = evolve.adjoint(orc, states.coherent_state(orc, alpha), dt, nsteps, evolve.objective_Q(orc))
+    tan = fh.tangent_rk4(model, b, fh.init_coherent(b, alpha), dt, nsteps, fh.FH_J_Q)
+    adj = fh.adjoint_rk4(model, b, fh.init_coherent(b, alpha), dt, nsteps, 5, fh.FH_J_Q)
+    assert abs(tan["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
+    assert abs(tan["dLambda"][0] - adj["dLambda"][0]) <= 1e-10 * max(1, abs(adj["dLambda"][0]))
