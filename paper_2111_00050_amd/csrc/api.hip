@@ -60,6 +60,15 @@ int persistent_grid(const fh_basis* b, const void* fn, size_t lds, int ntiles) {
     return (int)G;
 }
 
+// Walk order 3 takes the units from per-XCD counters only where every
+// workgroup takes many of them: a short launch (a few units per workgroup)
+// walks statically (as order 1), without the counter fill and the
+// per-unit barriers and atomics, which there cost more than the locality gains.
+constexpr int kQueueMinUnitsPerBlock = 16;
+bool use_queue(const fh_basis* b, long long units, int grid) {
+    return b->xcd_order == 3 && (grid & 7) == 0 && units >= (long long)kQueueMinUnitsPerBlock * grid;
+}
+
 }  // namespace fh
 
 using namespace fh;
@@ -427,7 +436,7 @@ StageArgs stage_base(const fh_model* m, const fh_basis* b) {
     a.nsqrt = (int)b->sqrt_tab.size();
     a.secs = b->d_secs;
     a.xcd_order = b->xcd_order;
-    a.queue = b->d_queue;
+    a.queue = nullptr;  // chosen per launch
     return a;
 }
 
@@ -509,7 +518,7 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
             if (nt == 0) continue;
             a.tiles = b->d_tiles + b->tile_begin[sec];
             a.ntiles = nt;
-            a.queue = nullptr;  // per-sector launches walk their tiles as in order 2
+            a.queue = nullptr;  // per-sector launches walk their tiles statically (order 3 as order 1)
             b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
         }
     } else {
@@ -517,12 +526,14 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
         if (nt > 0) {
             a.tiles = b->d_tiles;
             a.ntiles = nt;
-            if (a.xcd_order == 3) {
+            const int grid = persistent_grid(b, fn, lds, nt * G);
+            a.queue = use_queue(b, nt * G, grid) ? b->d_queue : nullptr;
+            if (a.queue) {
                 // the eight XCD counters start at zero (a fill kernel: also valid under graph capture)
                 launch_fill(reinterpret_cast<double*>(b->d_queue), 4, 0.0, s);
                 FH_HIP(hipGetLastError());
             }
-            b->ks->stage[slot](a, persistent_grid(b, fn, lds, nt * G), lds, s);
+            b->ks->stage[slot](a, grid, lds, s);
         }
     }
     FH_HIP(hipGetLastError());
@@ -1294,8 +1305,8 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
     a.partial = b->d_partial;
     a.xcd_order = b->xcd_order;
     a.occ = b->d_occ;
-    a.queue = b->d_queue;
     const int G = persistent_grid(b, b->ks->corr_fn, lds, nt);
+    a.queue = use_queue(b, nt, G) ? b->d_queue : nullptr;
     const int per = corr_pairs_per_launch(M);
     for (int p0 = 0; p0 < kCorrPairs; p0 += per) {
         for (int q = 0; q < per; ++q) {
@@ -1303,7 +1314,7 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
             a.y[q] = y[p0 + q];
             a.uscale[q] = uscale[p0 + q];
         }
-        if (a.xcd_order == 3) {
+        if (a.queue) {
             launch_fill(reinterpret_cast<double*>(b->d_queue), 4 * M, 0.0, s);  // counters [class][XCD] = 0
             FH_HIP(hipGetLastError());
         }

@@ -41,12 +41,13 @@ constexpr FH_HD int stage_lanes_per_row(int nrhs) { return nrhs >= 4 ? 4 : nrhs;
 // registers per thread at 512 / (4 * blocks) per SIMD lane.
 constexpr int kStageBlocksPerCU = FH_STAGE_BLOCKS_PER_CU;
 // Minimum workgroups per CU the one-column stage kernel is compiled for: the
-// occupancy its register count reaches without the tile-queue loop (M <= 6:
-// <= 128 VGPRs, 4 waves per SIMD; M = 7, 8: <= 168, 3; M >= 9: 2), so that the
-// queue's few extra registers do not cost a wave per SIMD.  Several columns:
-// no bound (the 16-column kernel holds 256 VGPRs at one wave).
+// occupancy its register count reaches without the tile-queue loop (M <= 3:
+// 8 waves per SIMD; M = 4: <= 80 VGPRs, 6; M = 5: <= 96, 5; M = 6: <= 128, 4;
+// M = 7, 8: <= 168, 3; M >= 9: 2), so that the queue's few extra registers do
+// not cost a wave per SIMD.  Several columns: no bound (the 16-column kernel
+// holds 256 VGPRs at one wave).
 constexpr FH_HD int stage_min_blocks(int M, int nrhs) {
-    return nrhs > 1 ? kStageBlocksPerCU : (M <= 6 ? 4 : M <= 8 ? 3 : 2);
+    return nrhs > 1 ? kStageBlocksPerCU : (M <= 3 ? 8 : M == 4 ? 6 : M == 5 ? 5 : M == 6 ? 4 : M <= 8 ? 3 : 2);
 }
 
 template <int M>
@@ -153,7 +154,7 @@ struct StageArgs {
     int ntiles;
     const SecInfo* secs;
     int xcd_order;
-    unsigned* queue;      // xcd_order 3, 4: one tile counter per XCD, zero at launch
+    unsigned* queue;      // xcd_order 3: one tile counter per XCD, zero at launch; null: static walk
 };
 
 // Moments / one-body kernels.

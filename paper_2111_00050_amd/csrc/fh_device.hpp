@@ -243,7 +243,9 @@ __device__ __forceinline__ void load_occ(const unsigned char* occ, long long sta
 }
 
 // ------------------------------------------------------------ H psi stage --
-template <int M, int NRHS>
+// QUEUE: the variant that takes its units from the per-XCD counters (order 3
+// with counters); the static walks are compiled without the counter loop.
+template <int M, int NRHS, bool QUEUE>
 __global__ __launch_bounds__(kTileRows, stage_min_blocks(M, NRHS)) void stage_kernel(StageArgs A) {
     using CB = Combos<M>;
     constexpr int NP = CB::NP;
@@ -277,13 +279,10 @@ __global__ __launch_bounds__(kTileRows, stage_min_blocks(M, NRHS)) void stage_ke
     const __attribute__((address_space(4))) SecInfo* secs =
         (const __attribute__((address_space(4))) SecInfo*)A.secs;
     const UnitWalk walk = unit_walk(A.xcd_order, A.ntiles * G);
-    // Order 3: the next unit of this XCD's eighth comes from its counter (one
-    // vector atomic per workgroup and unit); every workgroup leaves once the
-    // counter has passed the end of the eighth.
     // Order 3: the next unit comes from this XCD's counter (one vector atomic
     // per workgroup and unit); every workgroup leaves once its XCD has no unit
     // left.
-    const bool queued = A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
+    const bool queued = QUEUE && A.xcd_order == 3 && A.queue != nullptr && (gridDim.x & 7) == 0;
     __shared__ int s_unit;
     for (int vt = walk.first;; vt += walk.step) {
         if (queued) {

@@ -67,6 +67,7 @@ void set_error(const std::string& msg);
 fh_status hip_fail(hipError_t e, const char* what);
 size_t lds_bytes(const fh_basis* b, int extra_doubles);
 int persistent_grid(const fh_basis* b, const void* fn, size_t lds, int ntiles);
+bool use_queue(const fh_basis* b, long long units, int grid);
 int moments_grid(const fh_basis* b, size_t* lds);
 fh_status moments_core(const fh_basis* b, int nrhs, int rhs, const double* psi, double* rec, hipStream_t s,
                        int groups, double* partial, double* reduced, double* v);

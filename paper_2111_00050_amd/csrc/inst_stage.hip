@@ -1,4 +1,5 @@
-// inst_stage.hip -- instantiates the H psi stage kernel for one (M, nrhs).
+// inst_stage.hip -- instantiates the H psi stage kernel for one (M, nrhs):
+// the static-walk variant and the per-XCD counter variant.
 // Compiled once per pair with -DFH_INST_M=<M> -DFH_INST_R=<nrhs>.
 #include "fh_device.hpp"
 #include "fh_launch.hpp"
@@ -13,11 +14,14 @@
 namespace fh {
 namespace {
 void launch(const StageArgs& a, int grid, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R>), dim3(grid), dim3(kTileRows), lds, s, a);
+    if (a.queue)
+        hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, true>), dim3(grid), dim3(kTileRows), lds, s, a);
+    else
+        hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, false>), dim3(grid), dim3(kTileRows), lds, s, a);
 }
 }  // namespace
 
 StageEntry FH_CAT4(stage_entry_M, FH_INST_M, _R, FH_INST_R)() {
-    return StageEntry{reinterpret_cast<const void*>(&stage_kernel<FH_INST_M, FH_INST_R>), &launch};
+    return StageEntry{reinterpret_cast<const void*>(&stage_kernel<FH_INST_M, FH_INST_R, false>), &launch};
 }
 }  // namespace fh
