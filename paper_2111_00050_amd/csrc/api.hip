@@ -1282,6 +1282,22 @@ int class_rank(int M, int i, int j) {
     return -1;
 }
 
+// Workgroups per momentum class of a correlator launch (grid Gc x M,
+// blockIdx.y the class), from the resident grid G of the launch.  A long
+// launch (at least 16 tiles per resident workgroup) gives every class all of G,
+// so that the classes run one after another and each sweep's gather footprint
+// is that of one class's moves (running them side by side was slower there:
+// the 55.5M-state M = 6 adjoint took 3.67 instead of 3.44 forward runs).  A
+// short launch gives each class G / M (at most one per tile), so that all
+// classes run at once and every workgroup takes several tiles and stages its
+// tables once for them (with one workgroup per tile and class most of them
+// waited for a slot: the 54k-state M = 6 adjoint took 3.45 forward runs, now
+// 2.73).
+int corr_class_grid(int M, int G, int ntiles) {
+    if ((long long)ntiles >= 16LL * G) return G;
+    return std::max(1, std::min(ntiles, G / M));
+}
+
 // gtotal += correlators of the kCorrPairs pairs (uscale[q] u[q], y[q]) for column rhs.
 fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u)[kCorrPairs],
                    const double (&uscale)[kCorrPairs], const double* const (&y)[kCorrPairs], double* gtotal,
@@ -1305,7 +1321,7 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
     a.partial = b->d_partial;
     a.xcd_order = b->xcd_order;
     a.occ = b->d_occ;
-    const int G = persistent_grid(b, b->ks->corr_fn, lds, nt);
+    const int G = corr_class_grid(M, persistent_grid(b, b->ks->corr_fn, lds, nt * M), nt);
     a.queue = use_queue(b, nt, G) ? b->d_queue : nullptr;
     const int per = corr_pairs_per_launch(M);
     for (int p0 = 0; p0 < kCorrPairs; p0 += per) {
