@@ -1027,3 +1027,46 @@ def test_tangent_at_tiny_interaction():
     adj = fh.adjoint_rk4(model, b, fh.init_coherent(b, alpha), dt, nsteps, 5, fh.FH_J_Q)
     assert abs(tan["dLambda"][0] - ref["dLambda"]) <= 1e-9 * max(1, abs(ref["dLambda"]))
     assert abs(tan["dLambda"][0] - adj["dLambda"][0]) <= 1e-10 * max(1, abs(adj["dLambda"][0]))
+
+
+@pytest.mark.parametrize("which", ["large_sector", "fieldnumber_draw"])
+def test_rk4_steps_full_size(which):
+    """Full size, in the benchmark's launch configuration (basis default:
+    counter walk, every workgroup the CU holds; FH_TIMING): the one large
+    sector (M=8, N=48, P=0, 25.4M states) and one field-number draw (M=10,
+    N=30, all P, 212M states), one column.  Sampled rows of a plain H psi
+    launch (APPLY) against the oracle; then two fused RK4 steps (FIRST, MID,
+    MID, LAST epilogues) against the classical RK4 combination of APPLY
+    launches, to rounding; the moments recorded after the last step equal
+    those of the composed state."""
+    w = W.large_sector() if which == "large_sector" else W.fieldnumber_draws(16, 30)
+    orc = Oracle(w.M, w.pmod, w.omega, w.Lambda, w.V, w.sectors)
+    model = fh.Model(w.M, w.omega, w.Lambda, w.V)
+    b = fh.Basis(w.M, w.sectors)
+    assert b.total == orc.total
+    x0 = W.periodic_psi(b.total, 23)
+    x0 /= np.linalg.norm(x0)
+    rows = _sample_rows(orc, np.random.default_rng(17), 2000)
+    x = torch.from_numpy(x0).cuda()
+    hx = fh.apply_h(model, b, x)
+    want = orc.apply_h_rows(x0, rows)
+    assert np.abs(hx[torch.from_numpy(rows).cuda()].cpu().numpy() - want).max() <= 1e-13 * np.abs(want).max()
+    del hx, x0, orc
+    psi = x.clone()
+    res = fh.evolve_rk4(model, b, psi, w.dt, 2, every=1, flags=fh.FH_TIMING)
+    y = x
+    for _ in range(2):
+        k1 = -1j * fh.apply_h(model, b, y)
+        k2 = -1j * fh.apply_h(model, b, y + (w.dt / 2) * k1)
+        k3 = -1j * fh.apply_h(model, b, y + (w.dt / 2) * k2)
+        k4 = -1j * fh.apply_h(model, b, y + w.dt * k3)
+        y = y + (w.dt / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
+        del k1, k2, k3, k4
+    assert float(torch.linalg.vector_norm(psi - y)) <= 1e-13
+    # the moments recorded after the last step equal those of the composed state
+    assert len(res.records) == 3
+    n2, a, Mm, A = fh.unpack_moments(w.M, res.records[-1, 0])
+    wn2, wa, wM, wA = fh.moments(b, y)
+    assert abs(n2 - wn2) <= 1e-13
+    for g_, w_ in ((a, wa), (Mm, wM), (A, wA)):
+        assert np.abs(np.asarray(g_) - np.asarray(w_)).max() <= 1e-10 * max(1.0, np.abs(np.asarray(w_)).max())
