@@ -246,8 +246,12 @@ fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c
  * chunks of order 1, each XCD taking the tiles of its chunks in order from a
  * counter of that XCD, so that the tiles in flight on an XCD stay one compact
  * run; with order 3 the counters live in the basis, so stage and adjoint
- * launches on one basis must not overlap on different streams).  A new basis
- * starts at (0, 3).
+ * launches on one basis must not overlap on different streams).  Order 3 uses
+ * the counters only on launches where every workgroup takes at least 16 tiles;
+ * shorter launches walk as order 1.  With the counters, which workgroup sums
+ * which tile varies between runs, so the adjoint's correlator sums (dJ/dV,
+ * dJ/dLambda at M <= 7) can differ in the last bits from run to run; states
+ * and moments do not.  A new basis starts at (0, 3).
  * Not thread-safe with concurrent calls on the same basis. */
 fh_status fh_basis_set_launch(fh_basis* b, int blocks_per_cu, int xcd_order);
 /* Tiling and schedule of each sector's rows; storage stays lexicographic and
