@@ -1299,9 +1299,14 @@ int corr_class_grid(int M, int G, int ntiles) {
 }
 
 // gtotal += correlators of the kCorrPairs pairs (uscale[q] u[q], y[q]) for column rhs.
+// With several columns and at least 2 x (pairs per launch) single-column
+// buffers in colbuf, each launch's u and y columns are first copied out
+// contiguous and the launch runs as for one column (its buffer-load gathers
+// then read whole lines of the one column instead of every nrhs-th 16 bytes;
+// the launches and their sums are those of a one-column run, bit for bit).
 fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u)[kCorrPairs],
                    const double (&uscale)[kCorrPairs], const double* const (&y)[kCorrPairs], double* gtotal,
-                   hipStream_t s) {
+                   hipStream_t s, double* const* colbuf = nullptr, int ncolbuf = 0) {
     const int nt = (int)b->tiles.size();
     if (nt == 0) return FH_OK;
     const int M = b->M;
@@ -1324,11 +1329,23 @@ fh_status run_corr(const fh_basis* b, int nrhs, int rhs, const double* const (&u
     const int G = corr_class_grid(M, persistent_grid(b, b->ks->corr_fn, lds, nt * M), nt);
     a.queue = use_queue(b, nt, G) ? b->d_queue : nullptr;
     const int per = corr_pairs_per_launch(M);
+    const bool take = nrhs > 1 && colbuf != nullptr && ncolbuf >= 2 * per;
+    if (take) {
+        a.nrhs = 1;
+        a.rhs = 0;
+    }
     for (int p0 = 0; p0 < kCorrPairs; p0 += per) {
         for (int q = 0; q < per; ++q) {
             a.u[q] = u[p0 + q];
             a.y[q] = y[p0 + q];
             a.uscale[q] = uscale[p0 + q];
+            if (take) {
+                launch_take_column(u[p0 + q], colbuf[q], b->total, nrhs, rhs, s);
+                launch_take_column(y[p0 + q], colbuf[per + q], b->total, nrhs, rhs, s);
+                FH_HIP(hipGetLastError());
+                a.u[q] = colbuf[q];
+                a.y[q] = colbuf[per + q];
+            }
         }
         if (a.queue) {
             launch_fill(reinterpret_cast<double*>(b->d_queue), 4 * M, 0.0, s);  // counters [class][XCD] = 0
@@ -1562,6 +1579,17 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         FH_REQUIRE(gt_per * nrhs + 8192 <= b->small_doubles, FH_EUNSUPPORTED, "adjoint: scratch too small");
         launch_fill(gtot, (long long)(gt_per * nrhs), 0.0, s);
 
+        // Single-column buffers for the correlators of several columns, carved
+        // from scratch vectors the reverse sweep leaves free (yA and yB; with
+        // kept stage inputs also y2, y3, y4): nrhs columns each.
+        std::vector<double*> colbuf;
+        if (nrhs > 1) {
+            std::vector<double*> freev = {yA, yB};
+            if (keep) freev.insert(freev.end(), {y2, y3, y4});
+            for (double* v : freev)
+                for (int c = 0; c < nrhs; ++c) colbuf.push_back(v + (int64_t)c * 2 * b->total);
+        }
+
         StageArgs ab = stage_base(mT, b);
         ab.ks_re = 0.0;
         ab.ks_im = 1.0;
@@ -1611,7 +1639,8 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
                     const double sc[kCorrPairs] = {dt / 6, 1.0, 1.0, 1.0};
                     const double* ys[kCorrPairs] = {s4p, s3p, s2p, ps};
                     for (int q = 0; q < nrhs; ++q) {
-                        st = run_corr(b, nrhs, q, us, sc, ys, gtot + q * gt_per, s);
+                        st = run_corr(b, nrhs, q, us, sc, ys, gtot + q * gt_per, s, colbuf.data(),
+                                      (int)colbuf.size());
                         if (st != FH_OK) return st;
                     }
                 }

@@ -97,5 +97,7 @@ void launch_cscale(double* out, const double* in, long long n, double re, double
 void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s);
 // psi[i*nrhs + q] *= scale[q]
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s);
+// out = column q of the total x nrhs complex vector in, contiguous (total complex).
+void launch_take_column(const double* in, double* out, long long total, int nrhs, int q, hipStream_t s);
 
 }  // namespace fh

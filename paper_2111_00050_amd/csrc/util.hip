@@ -40,6 +40,15 @@ __global__ void scale_rhs_kernel(double* psi, long long total, int nrhs, const d
     }
 }
 
+// out[i] = in[i * nrhs + q], i < total (complex): one column of a
+// several-column vector, contiguous.
+__global__ void take_column_kernel(const double2* __restrict__ in, double2* __restrict__ out, long long total,
+                                   int nrhs, int q) {
+    const long long stride = (long long)gridDim.x * blockDim.x;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+        out[i] = in[i * nrhs + q];
+}
+
 // RK4 stage of the tangent z = d psi / d Lambda:  k = -i (hz + gy) with
 // hz = H z_s and gy = G y_s already applied; epilogue as in the fused stage:
 //   FIRST: acc = base + a k, next = c0 base + b k;  MID: acc += a k,
@@ -242,6 +251,11 @@ void launch_cscale(double* out, const double* in, long long n, double re, double
 }
 void launch_hash_fill(double* x, long long n, unsigned long long seed, hipStream_t s) {
     if (n > 0) hipLaunchKernelGGL(hash_fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, n, seed);
+}
+void launch_take_column(const double* in, double* out, long long total, int nrhs, int q, hipStream_t s) {
+    if (total > 0)
+        hipLaunchKernelGGL(take_column_kernel, dim3(grid_for(total)), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(in), reinterpret_cast<double2*>(out), total, nrhs, q);
 }
 void launch_scale_rhs(double* psi, long long total, int nrhs, const double* scale, hipStream_t s) {
     if (total > 0)
