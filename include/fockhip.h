@@ -247,8 +247,8 @@ fh_status fh_evolve_taylor2(const fh_model* m, const fh_basis* b, int nrhs, fh_c
  * counter of that XCD, so that the tiles in flight on an XCD stay one compact
  * run; with order 3 the counters live in the basis, so stage and adjoint
  * launches on one basis must not overlap on different streams).  Order 3 uses
- * the counters only on launches where every workgroup takes at least 16 tiles;
- * shorter launches walk as order 1.  With the counters, which workgroup sums
+ * the counters only on launches where every workgroup takes at least 16 tiles,
+ * and in the H psi stages only from M = 7 on; otherwise it walks as order 1.  With the counters, which workgroup sums
  * which tile varies between runs, so the adjoint's correlator sums (dJ/dV,
  * dJ/dLambda at M <= 7) can differ in the last bits from run to run; states
  * and moments do not.  A new basis starts at (0, 3).

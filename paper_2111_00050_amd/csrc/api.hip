@@ -527,7 +527,7 @@ fh_status launch_stage(const fh_basis* b, int nrhs, StageArgs a, int flags, hipS
             a.tiles = b->d_tiles;
             a.ntiles = nt;
             const int grid = persistent_grid(b, fn, lds, nt * G);
-            a.queue = use_queue(b, nt * G, grid) ? b->d_queue : nullptr;
+            a.queue = b->M >= kStageCounterMinM && use_queue(b, nt * G, grid) ? b->d_queue : nullptr;
             if (a.queue) {
                 // the eight XCD counters start at zero (a fill kernel: also valid under graph capture)
                 launch_fill(reinterpret_cast<double*>(b->d_queue), 4, 0.0, s);

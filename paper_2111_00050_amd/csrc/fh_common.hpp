@@ -46,6 +46,11 @@ constexpr int kStageBlocksPerCU = FH_STAGE_BLOCKS_PER_CU;
 // M = 7, 8: <= 168, 3; M >= 9: 2), so that the queue's few extra registers do
 // not cost a wave per SIMD.  Several columns: no bound (the 16-column kernel
 // holds 256 VGPRs at one wave).
+// The stage kernel's counter walk (XCD order 3) pays from M = 7 on; at M <= 6
+// (54 gathers per row or fewer) the static walk of order 1 is faster (M = 6:
+// 4.20 against 4.66 ms per H psi on 55.5M states), and the counter variant is
+// not built.
+constexpr int kStageCounterMinM = 7;
 constexpr FH_HD int stage_min_blocks(int M, int nrhs) {
     return nrhs > 1 ? kStageBlocksPerCU : (M <= 3 ? 8 : M == 4 ? 6 : M == 5 ? 5 : M == 6 ? 4 : M <= 8 ? 3 : 2);
 }

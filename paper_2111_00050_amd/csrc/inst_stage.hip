@@ -1,5 +1,5 @@
 // inst_stage.hip -- instantiates the H psi stage kernel for one (M, nrhs):
-// the static-walk variant and the per-XCD counter variant.
+// the static-walk variant and, from M = 7 on, the per-XCD counter variant.
 // Compiled once per pair with -DFH_INST_M=<M> -DFH_INST_R=<nrhs>.
 #include "fh_device.hpp"
 #include "fh_launch.hpp"
@@ -14,10 +14,13 @@
 namespace fh {
 namespace {
 void launch(const StageArgs& a, int grid, size_t lds, hipStream_t s) {
-    if (a.queue)
-        hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, true>), dim3(grid), dim3(kTileRows), lds, s, a);
-    else
-        hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, false>), dim3(grid), dim3(kTileRows), lds, s, a);
+    if constexpr (FH_INST_M >= kStageCounterMinM) {
+        if (a.queue) {
+            hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, true>), dim3(grid), dim3(kTileRows), lds, s, a);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((stage_kernel<FH_INST_M, FH_INST_R, false>), dim3(grid), dim3(kTileRows), lds, s, a);
 }
 }  // namespace
 
