@@ -1070,3 +1070,31 @@ def test_rk4_steps_full_size(which):
     assert abs(n2 - wn2) <= 1e-13
     for g_, w_ in ((a, wa), (Mm, wM), (A, wA)):
         assert np.abs(np.asarray(g_) - np.asarray(w_)).max() <= 1e-10 * max(1.0, np.abs(np.asarray(w_)).max())
+
+
+def test_adjoint_chunked_correlators_on_the_benchmark_sector():
+    """The correlators of the adjoint at M >= 8 run over chunks of 2^24 rows;
+    the benchmark's sector (25.4M states) spans two.  dJ/dLambda of the
+    adjoint (which sums the correlators) against the forward-mode tangent
+    (which does not use them) and against a central difference of GPU forward
+    runs, for J = <n_0>(T) after 3 steps from a seeded vector."""
+    w = W.large_sector()
+    model = fh.Model(w.M, w.omega, w.Lambda, w.V)
+    b = fh.Basis(w.M, w.sectors)
+    assert b.total > (1 << 24)
+    x = torch.from_numpy(W.periodic_psi(b.total, 29)).cuda()
+    x /= torch.linalg.vector_norm(x)
+    dt, nsteps = w.dt, 3
+    adj = fh.adjoint_rk4(model, b, x, dt, nsteps, nsteps, fh.FH_J_NMODE, 0)
+    tan = fh.tangent_rk4(model, b, x, dt, nsteps, fh.FH_J_NMODE, 0)
+    assert abs(adj["J"][0] - tan["J"][0]) <= 1e-12 * abs(tan["J"][0])
+    assert abs(adj["dLambda"][0] - tan["dLambda"][0]) <= 1e-10 * abs(tan["dLambda"][0])
+    # J ~ 6 is summed to ~1e-15 relative, so the step must keep that rounding
+    # (6e-15 / 2h) well under the tolerance
+    h = 1e-2 * abs(w.Lambda)
+    Jpm = []
+    for sgn in (1, -1):
+        m2 = fh.Model(w.M, w.omega, w.Lambda + sgn * h, w.V)
+        Jpm.append(float(fh.adjoint_rk4(m2, b, x, dt, nsteps, nsteps, fh.FH_J_NMODE, 0)["J"][0]))
+    cd = (Jpm[0] - Jpm[1]) / (2 * h)
+    assert abs(adj["dLambda"][0] - cd) <= 1e-5 * abs(cd)
