@@ -1293,11 +1293,13 @@ int class_rank(int M, int i, int j) {
 // tables once for them (with one workgroup per tile and class most of them
 // waited for a slot: the 54k-state M = 6 adjoint took 3.45 forward runs, now
 // 2.73).
-constexpr long long kCorrChunkRows = 1LL << 24;
 int corr_class_grid(int M, int G, int ntiles) {
     if ((long long)ntiles >= 16LL * G) return G;
     return std::max(1, std::min(ntiles, G / M));
 }
+
+// Rows per correlator launch where the classes walk statically (run_corr).
+constexpr long long kCorrChunkRows = 1LL << 24;
 
 // gtotal += correlators of the kCorrPairs pairs (uscale[q] u[q], y[q]) for column rhs.
 // With several columns and at least 2 x (pairs per launch) single-column
