@@ -218,6 +218,8 @@ struct OccArgs {
 // Quartic correlators  G[c][(p1,p2)] = sum_q sum_n conj(uscale_q u_q(n)) <n|a_i^+ a_j^+ a_k a_l|n'> y_q(n')
 // for pairs p1 = {i,j}, p2 = {k,l} of class c (p1 == p2 included), summed over
 // kCorrPairs vector pairs (u_q, y_q) at once (the four stages of an adjoint step).
+// Only Im G is computed (the real parts are written as 0): with V real the
+// gradients need Im G alone.
 constexpr int kCorrPairs = 4;
 // pairs handled by one correlator launch (registers: M >= 9 has classes of 6 pairs)
 constexpr FH_HD int corr_pairs_per_launch(int M) { return M >= 9 ? 2 : kCorrPairs; }

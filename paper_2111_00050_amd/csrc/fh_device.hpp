@@ -712,7 +712,9 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     using CB = Combos<M>;
     constexpr int S = CB::class_size(C);
     constexpr int SMAX = CB::max_class_size();
-    constexpr int NV = 2 * S * S;
+    // Only the imaginary parts are summed: with V real, dJ/dV and dJ/dLambda
+    // need Im <u|X|y> alone.  One double per pair of pairs.
+    constexpr int NV = S * S;
     constexpr int NPR = corr_pairs_per_launch(M);  // the launch's pairs are u[0..NPR), y[0..NPR)
     extern __shared__ int smem[];
     int* sT = smem;
@@ -723,15 +725,12 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     double acc[NV];
 #pragma unroll
     for (int q = 0; q < NV; ++q) acc[q] = 0.0;
-    // conj(u) y summed over the pairs
-    auto cdot = [](const double2 (&u)[NPR], const double2 (&y)[NPR], double& tr, double& ti) {
-        tr = 0.0;
-        ti = 0.0;
+    // Im(conj(u) y) summed over the pairs
+    auto cdot_im = [](const double2 (&u)[NPR], const double2 (&y)[NPR]) {
+        double ti = 0.0;
 #pragma unroll
-        for (int p = 0; p < NPR; ++p) {
-            tr = fma(u[p].x, y[p].x, fma(u[p].y, y[p].y, tr));
-            ti = fma(u[p].x, y[p].y, fma(-u[p].y, y[p].x, ti));
-        }
+        for (int p = 0; p < NPR; ++p) ti = fma(u[p].x, y[p].y, fma(-u[p].y, y[p].x, ti));
+        return ti;
     };
     const __attribute__((address_space(4))) Tile* tiles = (const __attribute__((address_space(4))) Tile*)A.tiles;
     const __attribute__((address_space(4))) SecInfo* secs =
@@ -798,14 +797,11 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
         });
         {
             // p1 == p2: <n|a_i^+ a_j^+ a_i a_j|n> = c_ij^2
-            double tr, ti;
-            cdot(u, y0, tr, ti);
+            const double ti = cdot_im(u, y0);
             static_for<0, S>([&](auto R1) {
                 constexpr int r1 = decltype(R1)::value;
-                constexpr int o = 2 * (r1 * S + r1);
-                const double c2 = cij[r1] * cij[r1];
-                acc[o] = fma(c2, tr, acc[o]);
-                acc[o + 1] = fma(c2, ti, acc[o + 1]);
+                constexpr int o = r1 * S + r1;
+                acc[o] = fma(cij[r1] * cij[r1], ti, acc[o]);
             });
         }
         if constexpr (S > 1) {
@@ -865,12 +861,8 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
                 static_for<0, NQC>([&](auto Q) {
                     constexpr int q = q0 + decltype(Q)::value;
                     constexpr int r1 = q / (S - 1), tq = q % (S - 1), r2 = tq < r1 ? tq : tq + 1;
-                    constexpr int o = 2 * (r1 * S + r2);
-                    double tr, ti;
-                    cdot(u, v[decltype(Q)::value], tr, ti);
-                    const double w = cij[r1] * ckl[r2];
-                    acc[o] = fma(w, tr, acc[o]);
-                    acc[o + 1] = fma(w, ti, acc[o + 1]);
+                    constexpr int o = r1 * S + r2;
+                    acc[o] = fma(cij[r1] * ckl[r2], cdot_im(u, v[decltype(Q)::value]), acc[o]);
                 });
                 asm volatile("" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
@@ -882,7 +874,7 @@ __device__ __forceinline__ void corr_class(const CorrArgs& A) {
     if ((int)threadIdx.x < 2 * kCorrOutMax) {
         const int part = threadIdx.x & 1, slot = threadIdx.x >> 1;
         const int r1 = slot / SMAX, r2 = slot % SMAX;
-        const double v = (r1 < S && r2 < S) ? outv[2 * (r1 * S + r2) + part] : 0.0;
+        const double v = (part == 1 && r1 < S && r2 < S) ? outv[r1 * S + r2] : 0.0;  // real parts: 0
         A.partial[((size_t)C * gridDim.x + blockIdx.x) * 2 * kCorrOutMax + threadIdx.x] = v;
     }
 }
