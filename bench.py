@@ -84,17 +84,16 @@ def _oracle_rows_worker(job):
 
 def adjoint_checkpoints(torch, nsteps: int, vec_bytes: int, frac: float = 0.8):
     """Checkpoint interval for fh_adjoint_rk4 that uses the free device memory.
-    With kept stage inputs the last segment is kept from the forward sweep and
-    every other segment is recomputed once, so the recompute is (segments - 1)
-    x C steps: take the fewest segments, each of C = ceil(nsteps / segments)
-    steps, whose work buffer (segments + 4C + 10 state vectors) fits in frac of
-    what is free; else the largest C with recomputed stage inputs (segments +
-    C + 10).  Returns (C, kept)."""
+    With kept stage inputs the last segment (a whole one: the first takes the
+    remainder) is kept from the forward sweep and every other segment is
+    recomputed once, so the recompute is nsteps - C steps: take the largest C
+    whose work buffer (segments + 4C + 10 state vectors) fits in frac of what is
+    free; else the largest C with recomputed stage inputs (segments + C + 10).
+    Returns (C, kept)."""
     torch.cuda.empty_cache()  # blocks cached by torch count as free here
     free, _ = torch.cuda.mem_get_info()
     budget = frac * free
-    for nseg in range(1, nsteps + 1):
-        C = -(-nsteps // nseg)
+    for C in range(nsteps, 0, -1):
         if (-(-nsteps // C) + 4 * C + 10) * vec_bytes <= budget:
             return C, True
     for C in range(nsteps, 0, -1):

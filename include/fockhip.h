@@ -297,8 +297,10 @@ fh_status fh_classical_rk4(const fh_model* m, int ntraj, fh_c64* alpha, double d
  *   FH_J_Q      : Q of Eq. (Qparam)
  *   FH_J_PO     : 1 - lambda_p / n_tot (Eq. POcriterion)
  *   FH_J_NMODE  : <a_k^+ a_k> with k = obj_mode
- * Checkpoints every ckpt_every steps; inside a segment the states are
- * recomputed forward.  work: device scratch of at least
+ * Checkpoints split the run into segments of ckpt_every steps, the first
+ * segment taking the remainder; inside a segment the states are recomputed
+ * forward, except in the last one, whose states (and, when kept, stage inputs)
+ * the forward sweep leaves in place.  work: device scratch of at least
  * fh_adjoint_work_states(...) * total * nrhs fh_c64; with at least
  * fh_adjoint_work_states_kept(...) states the stage inputs of every step are
  * kept from that recompute instead of being computed again (three H psi per

@@ -1498,6 +1498,11 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         hipStream_t s = as_stream(stream);
         const int64_t C = std::min(ckpt_every, nsteps);
         const int64_t nseg = (nsteps + ckpt_every - 1) / ckpt_every;
+        // Segment lengths: the first segment takes the remainder and the others
+        // C steps each, so that the last one (reversed first and, with kept
+        // stage inputs, never recomputed) is a whole one.
+        const int64_t first_len = nsteps - (nseg - 1) * C;  // in [1, C]
+        auto seg_len = [&](int64_t k) { return k == 0 ? first_len : C; };
         // With room for 4 vectors per step of a segment, the stage inputs of
         // every step are kept from the segment's forward recompute instead of
         // being recomputed (3 H psi per step fewer).
@@ -1559,7 +1564,7 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
         FH_HIP(hipMemcpyAsync(buf(0), psi0, vbytes, hipMemcpyDeviceToDevice, s));
         FH_HIP(hipMemcpyAsync(run, psi0, vbytes, hipMemcpyDeviceToDevice, s));
         for (int64_t k = 0; k < nseg; ++k) {
-            const int64_t len = std::min(C, nsteps - k * C);
+            const int64_t len = seg_len(k);
             if (keep && k == nseg - 1) {
                 // state(0) is the checkpoint buf(k) (== run); states 1..len-1 go to
                 // the segment slots, psi_T to run
@@ -1619,7 +1624,7 @@ fh_status fh_adjoint_rk4(const fh_model* m, const fh_basis* b, int nrhs, const f
 
 
         for (int64_t k = nseg - 1; k >= 0; --k) {
-            const int64_t len = std::min(C, nsteps - k * C);
+            const int64_t len = seg_len(k);
             // state of step t of the segment: the checkpoint itself for t = 0
             auto state = [&](int64_t t) { return t == 0 ? buf(k) : segst(t); };
             // the last segment's states and stage inputs are already there
