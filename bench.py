@@ -559,15 +559,15 @@ def main():
     if args.warmup > 0:
         fh.evolve_rk4(model, basis, psi, w.dt, args.warmup, work=work)
     torch.cuda.synchronize()
-    # Moments every 50 steps as the workload asks (from step 0 on).  When the
-    # timed steps are not a multiple of 50 no such step falls inside them and
-    # the timed run records none; the drift checks then compare the moments
-    # of the first and the last timed state, taken outside the timed region.
+    # Moments every 50 steps as the workload asks, from step 0 on, all inside
+    # the timed region.  When the timed steps are not a multiple of 50, step 0
+    # is the only such step: its moments are timed on their own and the run
+    # records none; the drift checks compare them with the last state's
+    # moments, taken after the timed region (not a step of the cadence).
     every = w.every if args.steps % w.every == 0 else 0
-    rec0 = None if every else fh.moments(basis, psi)
-    torch.cuda.synchronize()
     print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
+    rec0 = None if every else fh.moments(basis, psi)
     res = fh.evolve_rk4(model, basis, psi, w.dt, args.steps, every=every, flags=fh.FH_TIMING, work=work)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
