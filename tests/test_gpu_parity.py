@@ -407,19 +407,23 @@ def test_autotune_changes_no_bit(tmp_path):
     assert np.array_equal(fh.apply_h(model, b2, x).cpu().numpy(), before)
 
 
-def test_adjoint_two_rhs_matches_single():
+@pytest.mark.parametrize("keep", [True, False])
+def test_adjoint_two_rhs_matches_single(keep):
     """Two coherent states adjointed together give, column by column, what
     each gives alone (the multi-rhs stage kernel sums each column in the
-    single-rhs order)."""
+    single-rhs order).  With kept stage inputs the correlators run on
+    contiguous copies of each column; without, at M = 4 (four pairs per
+    launch) two columns leave too few free scratch vectors for the copies and
+    the correlators gather every other 16 bytes of the interleaved vector."""
     M, Lam, dt, nsteps = 4, 0.3, 5e-3, 12
     omega, V = W.omega_quadratic(M), W.V_longrange(M)
     b = fh.Basis(M, W.all_sectors(M, 8))
     model = fh.Model(M, omega, Lam, V)
     al = np.stack([W.coherent_amplitudes(s, M, 1.3) for s in (61, 62)])
-    both = fh.adjoint_rk4(model, b, fh.init_coherent(b, al), dt, nsteps, 5, fh.FH_J_Q)
+    both = fh.adjoint_rk4(model, b, fh.init_coherent(b, al), dt, nsteps, 5, fh.FH_J_Q, keep_stage_inputs=keep)
     lam_both = both["lambda0"].cpu().numpy()
     for q in range(2):
-        one = fh.adjoint_rk4(model, b, fh.init_coherent(b, al[q]), dt, nsteps, 5, fh.FH_J_Q)
+        one = fh.adjoint_rk4(model, b, fh.init_coherent(b, al[q]), dt, nsteps, 5, fh.FH_J_Q, keep_stage_inputs=keep)
         assert abs(both["J"][q] - one["J"][0]) <= 1e-14
         assert abs(both["dLambda"][q] - one["dLambda"][0]) <= 1e-12 * max(1.0, abs(one["dLambda"][0]))
         assert np.abs(both["dV"][q] - one["dV"][0]).max() <= 1e-12 * max(1.0, np.abs(one["dV"][0]).max())
