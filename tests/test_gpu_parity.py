@@ -1102,3 +1102,34 @@ def test_adjoint_chunked_correlators_on_the_benchmark_sector():
         Jpm.append(float(fh.adjoint_rk4(m2, b, x, dt, nsteps, nsteps, fh.FH_J_NMODE, 0)["J"][0]))
     cd = (Jpm[0] - Jpm[1]) / (2 * h)
     assert abs(adj["dLambda"][0] - cd) <= 1e-5 * abs(cd)
+
+
+@pytest.mark.parametrize("M,N", [(7, 48), (9, 28)])
+def test_counter_walk_kernels_m7_m9(M, N):
+    """The counter-walk stage kernels of M = 7 and 9, which no benchmark
+    workload runs: one sector (N, P = 0) of 3.7M / 3.4M states, enough that
+    every workgroup takes at least 16 tiles.  Sampled rows of H psi against
+    the oracle; two fused RK4 steps against the RK4 combination of plain H psi
+    launches."""
+    omega, V, Lam, dt = W.omega_quadratic(M), W.V_longrange(M), 0.02, 5e-4
+    orc = Oracle(M, M, omega, Lam, V, [(N, 0)])
+    model, b = fh.Model(M, omega, Lam, V), fh.Basis(M, [(N, 0)])
+    assert b.total == orc.total and b.total // 256 >= 16 * 768
+    x0 = W.periodic_psi(b.total, 31 + M)
+    x0 /= np.linalg.norm(x0)
+    rows = _sample_rows(orc, np.random.default_rng(M), 1500)
+    x = torch.from_numpy(x0).cuda()
+    hx = fh.apply_h(model, b, x)
+    want = orc.apply_h_rows(x0, rows)
+    assert np.abs(hx[torch.from_numpy(rows).cuda()].cpu().numpy() - want).max() <= 1e-13 * np.abs(want).max()
+    del hx, x0, orc
+    psi = x.clone()
+    fh.evolve_rk4(model, b, psi, dt, 2)
+    y = x
+    for _ in range(2):
+        k1 = -1j * fh.apply_h(model, b, y)
+        k2 = -1j * fh.apply_h(model, b, y + (dt / 2) * k1)
+        k3 = -1j * fh.apply_h(model, b, y + (dt / 2) * k2)
+        k4 = -1j * fh.apply_h(model, b, y + dt * k3)
+        y = y + (dt / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
+    assert float(torch.linalg.vector_norm(psi - y)) <= 1e-13
