@@ -1133,3 +1133,22 @@ def test_counter_walk_kernels_m7_m9(M, N):
         k4 = -1j * fh.apply_h(model, b, y + dt * k3)
         y = y + (dt / 6) * (k1 + 2 * k2 + 2 * k3 + k4)
     assert float(torch.linalg.vector_norm(psi - y)) <= 1e-13
+
+
+@pytest.mark.parametrize("nrhs", [2, 4])
+def test_counter_walk_multi_column_bitwise(nrhs):
+    """Several columns under the counter walk (M = 8, N = 40, P = 0: 7.9M
+    states, every workgroup taking many tile passes): two fused RK4 steps of
+    an nrhs-column vector equal, column by column and bit for bit, the same
+    steps of each column alone."""
+    M = 8
+    w = W.large_sector()
+    model, b = fh.Model(M, w.omega, w.Lambda, w.V), fh.Basis(M, [(40, 0)])
+    assert b.total > 7_000_000
+    cols = [W.periodic_psi(b.total, 40 + q) for q in range(nrhs)]
+    X = torch.from_numpy(np.stack(cols, axis=1)).cuda().contiguous()
+    fh.evolve_rk4(model, b, X, w.dt, 2)
+    for q in range(nrhs):
+        one = torch.from_numpy(cols[q]).cuda()
+        fh.evolve_rk4(model, b, one, w.dt, 2)
+        assert torch.equal(X[:, q].contiguous(), one), q
